@@ -1,0 +1,209 @@
+/*
+ * vrn.h -- C ABI of the MI355X-native VR-NeRF renderer hot path
+ * (Xu et al., "VR-NeRF: High-Fidelity Virtualized Walkable Spaces",
+ * SIGGRAPH Asia 2023, arXiv 2311.02542).
+ *
+ * The library renders an instant-NGP-style radiance field ray by ray:
+ *   occupancy-bitfield lattice march (Sec. 4.3, "binary occupancy grid"),
+ *   multiresolution hash encoding with LOD mip-mapping (Sec. 4.2.1, Eq. 3;
+ *   dense coarse levels and skipped fine levels, App. D),
+ *   density MLP (1 hidden layer of 64) and color MLP (2 hidden layers of 64,
+ *   sigmoid in PQ units) (Sec. 5 and Sec. 6; Sec. 4.1),
+ *   front-to-back alpha compositing with early termination into an HDR
+ *   framebuffer of PQ values (Sec. 4.1, Eq. 1-2), optionally decoded to
+ *   linear HDR (linear 1.0 = 100 cd/m^2).
+ *
+ * Conventions
+ *   - Every pointer marked "host" is read during the call only; the library
+ *     keeps its own copies.  Pointers marked "device" are HIP device memory
+ *     owned by the caller.  hip_stream is a hipStream_t (NULL = default
+ *     stream).  Work is enqueued asynchronously on that stream; the caller
+ *     synchronises it before reading outputs.
+ *   - All functions return vrn_status.  Arguments are validated on the host
+ *     before anything is enqueued; on failure nothing is enqueued and
+ *     vrn_last_error() describes the problem.  Device faults surface as
+ *     VRN_ERR_DEVICE on the same or a later call.
+ *   - A context is guarded by one internal mutex; calls on one context from
+ *     several threads are serialised.  Renders that overlap on the device
+ *     (different streams) must use different workspaces.
+ *   - Sizes are in elements unless the name says bytes.
+ */
+#ifndef VRN_H
+#define VRN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vrn_ctx vrn_ctx;
+typedef uint32_t vrn_field_id;
+
+typedef enum {
+  VRN_OK = 0,
+  VRN_ERR_INVALID_ARG = -1,   /* NULL / NaN / degenerate / out-of-range argument */
+  VRN_ERR_UNSUPPORTED = -2,   /* valid but not implemented (e.g. F != 2, L > 16) */
+  VRN_ERR_OUT_OF_MEMORY = -3, /* hipMalloc failed */
+  VRN_ERR_BUDGET = -4,        /* would exceed the context's HBM budget */
+  VRN_ERR_DEVICE = -5,        /* no usable GPU, or a HIP runtime error */
+  VRN_ERR_NOT_FOUND = -6,     /* unknown field id */
+  VRN_ERR_BUSY = -7           /* field still has renders in flight */
+} vrn_status;
+
+typedef enum { VRN_F32 = 0, VRN_F16 = 1, VRN_BF16 = 2 } vrn_dtype;
+
+/* Everything that defines a field.  Host pointers; copied by vrn_load_field. */
+typedef struct {
+  uint32_t n_levels;          /* L, 1..16 hash-grid levels */
+  uint32_t log2_T;            /* table size T = 2^log2_T entries per level, 4..24 */
+  uint32_t n_feat;            /* F, must be 2 */
+  const uint32_t* level_res;  /* host [L]: integer lattice resolution N_l >= 1
+                                 (lattice of N_l + 1 points per axis; a level is
+                                 stored densely when (N_l + 1)^3 <= T) */
+  uint32_t hash_primes[3];    /* spatial hash (c0*p0 ^ c1*p1 ^ c2*p2) mod T */
+  float base_res;             /* s: LOD level-0 resolution (Sec. 4.2.1) */
+  float growth;               /* f: per-level scale factor, > 1 when lod_enable */
+  vrn_dtype table_dtype;      /* VRN_F32 or VRN_F16 */
+  const void* tables;         /* host [L][T][F], feature fastest, finite values */
+  uint32_t mlp_in;            /* density MLP input width, must be 2 * L */
+  uint32_t mlp_hidden;        /* must be 64 */
+  uint32_t geo_out;           /* density MLP output width, must be 16 (sigma + 15) */
+  uint32_t sh_bands;          /* direction SH bands, 1..4 (bands^2 coefficients) */
+  const float* weights;       /* host, concatenated row-major [in][out]:
+                                 W1[2L][64] b1[64] W2[64][16] b2[16]
+                                 W3[15+bands^2][64] b3[64] W4[64][64] b4[64]
+                                 W5[64][3] b5[3] */
+  uint32_t occ_res;           /* G, 1..1024 */
+  const uint32_t* occ_bits;   /* host, G^3 bits, bit i = x + G*(y + G*z), LSB first */
+  float aabb_min[3];          /* the field occupies the cube [aabb_min, aabb_min + extent] */
+  float extent;               /* > 0 */
+  float dt;                   /* lattice step: samples at t_k = (k + 1/2) dt, > 0 */
+  uint32_t max_samples;       /* cap on evaluated (occupied) samples per ray, >= 1 */
+  float t_min;                /* early termination once transmittance < t_min, [0, 1) */
+  int32_t lod_enable;         /* 0: all levels weight 1; 1: Eq. 3 weights */
+  float lod_bias;             /* Delta L added to L* (Sec. 4.2.2) */
+  float lod_radius_scale;     /* r = scale * distance of adjacent unit-distance ray points */
+} vrn_field_desc;
+
+/* One pinhole camera.  c2w is row-major 3x4 camera-to-world with OpenCV axes
+ * (+x right, +y down, +z forward); pixel centres at +0.5.  Only rows
+ * [row_begin, row_end) are rendered (one GPU's share of a frame); the
+ * framebuffer is still addressed as the full image. */
+typedef struct {
+  float c2w[12];
+  float fx, fy, cx, cy;
+  uint32_t row_begin, row_end;
+} vrn_camera;
+
+typedef struct {
+  vrn_dtype compute;          /* MLP arithmetic: VRN_F32 (FP32 MFMA), VRN_F16 or
+                                 VRN_BF16 (MFMA, FP32 accumulate); march,
+                                 transmittance and compositing are FP32 always */
+  int32_t output_linear_hdr;  /* 0: PQ RGB; 1: linear HDR (100 * PQ^-1 per channel) */
+  uint32_t march_budget;      /* lattice steps per march round, 0 = default */
+} vrn_render_opts;
+
+/* Work counters accumulated in a workspace by every render. */
+typedef struct {
+  uint64_t rays;              /* rays finished (pixels written) */
+  uint64_t samples;           /* evaluated samples composited */
+  uint64_t level_fetches;     /* hash levels gathered (8 corners each) */
+  uint64_t march_steps;       /* canonical lattice tests + block skips */
+} vrn_stats;
+
+#define VRN_MAX_CAMS 16
+
+/* Open device `device` (HIP ordinal).  hbm_budget_bytes bounds the memory of
+ * resident fields (0 = no bound).  VRN_ERR_DEVICE when no GPU is usable. */
+vrn_status vrn_create(int device, uint64_t hbm_budget_bytes, vrn_ctx** out);
+
+/* Free every field and internal buffer; waits for the device. NULL is a no-op. */
+void vrn_destroy(vrn_ctx* ctx);
+
+/* Thread-local description of the last failure on this thread. */
+const char* vrn_last_error(void);
+
+/* Validate a field and copy it into library-owned device memory (tables as
+ * given, occupancy bits plus a coarse block mip, MLP weights re-laid out for
+ * MFMA in FP32, FP16 and BF16).  The field stays resident until unloaded. */
+vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* desc, vrn_field_id* out);
+
+/* Free a field.  VRN_ERR_BUSY while renders that use it are still running. */
+vrn_status vrn_unload_field(vrn_ctx* ctx, vrn_field_id field);
+
+/* Device bytes held by a resident field. */
+vrn_status vrn_field_bytes(vrn_ctx* ctx, vrn_field_id field, uint64_t* out);
+
+/* Bytes of device workspace one render needs (counters, cameras, stats). */
+vrn_status vrn_workspace_bytes(vrn_ctx* ctx, uint64_t* out);
+
+/* Zero a caller-owned workspace with a kernel on hip_stream (safe inside
+ * graph capture).  Required once before a workspace's first render; a render
+ * leaves its counters at zero again, and the stats keep accumulating. */
+vrn_status vrn_workspace_init(vrn_ctx* ctx, void* d_workspace, uint64_t workspace_bytes,
+                              void* hip_stream);
+
+/* Render n_cams (1..VRN_MAX_CAMS) cameras of W x H pixels.
+ *   cams        host [n_cams]; validated (finite, det(R) != 0, fx, fy > 0,
+ *               row_begin < row_end <= H); copied into the workspace.
+ *   d_rgba      device [n_cams][H][W][4] float: PQ (or linear) RGB, alpha = 1 - T.
+ *   d_nsamples  device [n_cams][H][W] uint32 evaluated samples per pixel, or NULL.
+ *   d_workspace device, >= vrn_workspace_bytes, initialised once by
+ *               vrn_workspace_init; NULL uses the context's own workspace
+ *               (then renders on one context must not overlap).
+ * Only pixels in each camera's row share are written. */
+vrn_status vrn_render(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, uint32_t n_cams,
+                      uint32_t W, uint32_t H, const vrn_render_opts* opts, float* d_rgba,
+                      uint32_t* d_nsamples, void* d_workspace, uint64_t workspace_bytes,
+                      void* hip_stream);
+
+/* As vrn_render, but the cameras are already in device memory (d_cams,
+ * [n_cams] vrn_camera) and are NOT validated here (use vrn_check_cameras on
+ * the host copy).  Enqueues kernels only, so it can be captured in a HIP
+ * graph and replayed with new camera contents. */
+vrn_status vrn_render_device_cams(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* d_cams,
+                                  uint32_t n_cams, uint32_t W, uint32_t H,
+                                  const vrn_render_opts* opts, float* d_rgba, uint32_t* d_nsamples,
+                                  void* d_workspace, uint64_t workspace_bytes, void* hip_stream);
+
+/* Host-side camera validation used by vrn_render (no device work). */
+vrn_status vrn_check_cameras(const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H);
+
+/* Read (synchronously) the stats a workspace has accumulated. */
+vrn_status vrn_read_stats(vrn_ctx* ctx, const void* d_workspace, vrn_stats* out, void* hip_stream);
+
+/* ---- stage entry points: the same device code as vrn_render, one stage at
+ *      a time, for parity tests and profiling ---- */
+
+/* Canonical FP32 rays of every pixel of every camera, pixel order
+ * (cam, row, col): d_o, d_d device [n][3] float, d_r device [n] float cone
+ * pitch at unit distance (Sec. 4.2.1).  Cameras: host, validated. */
+vrn_status vrn_rays(vrn_ctx* ctx, const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H,
+                    float lod_radius_scale, float* d_o, float* d_d, float* d_r, void* hip_stream);
+
+/* Occupancy march without compositing (Sec. 4.3): for every pixel (cam, row,
+ * col) the evaluated lattice indices k in increasing order, capped at the
+ * field's max_samples and at max_k.  d_klist device [n][max_k] uint32,
+ * d_count device [n] uint32 (the uncapped-by-max_k count). */
+vrn_status vrn_march(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, uint32_t n_cams,
+                     uint32_t W, uint32_t H, uint32_t* d_klist, uint32_t max_k, uint32_t* d_count,
+                     void* hip_stream);
+
+/* Hash encoding with LOD (Sec. 4.2.1, App. D) of n world points d_xyz
+ * [n][3] at ray distance d_t [n] with cone pitch d_r [n] (both ignored when
+ * LOD is off): d_feat device [n][2L] float, level-major, feature fastest. */
+vrn_status vrn_encode(vrn_ctx* ctx, vrn_field_id field, const float* d_xyz, const float* d_t,
+                      const float* d_r, uint32_t n, float* d_feat, void* hip_stream);
+
+/* Density + color MLPs on MFMA in the requested dtype for n samples:
+ * d_feat [n][2L], d_dir [n][3] unit view directions -> d_sigma [n]
+ * (exp of density output 0), d_rgb [n][3] (sigmoid, PQ units). */
+vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const float* d_dir,
+                   uint32_t n, vrn_dtype compute, float* d_sigma, float* d_rgb, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VRN_H */

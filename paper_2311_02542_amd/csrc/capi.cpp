@@ -1,0 +1,598 @@
+// C ABI of the renderer (include/vrn.h): host validation, field residency,
+// MFMA weight layout, workspaces and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace vrn;
+
+namespace {
+
+thread_local std::string g_err;
+
+vrn_status fail(vrn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+vrn_status hip_fail(hipError_t e, const char* what) {
+  return fail(VRN_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Field {
+  FieldDev dev{};
+  std::vector<void*> allocs;
+  uint64_t bytes = 0;
+  std::vector<hipEvent_t> events;  // renders in flight
+};
+
+}  // namespace
+
+struct vrn_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  int n_cu = 0;
+  std::mutex mu;
+  std::map<uint32_t, Field*> fields;
+  uint32_t next_id = 1;
+  void* ws = nullptr;  // the context's own workspace
+};
+
+namespace {
+
+bool finite(float v) { return std::isfinite(v); }
+
+// ---- MFMA weight layout (mirrors the lane mapping documented in device.hpp)
+// Input index feeding element e of lane group g, per layer; -1 = zero weight.
+int in_index(int layer, int g, int e, int L, int nsh) {
+  switch (layer) {
+    case 0: {  // density layer 1: features of levels g + 4 (e >> 1)
+      const int lev = g + 4 * (e >> 1);
+      return lev < L ? 2 * lev + (e & 1) : -1;
+    }
+    case 2: {  // color layer 1: density outputs 4 g + e (output 0 = density), then SH g + 4 i
+      if (e < 4) {
+        const int o = 4 * g + e;
+        return o >= 1 ? o - 1 : -1;
+      }
+      const int c = g + 4 * (e - 4);
+      return c < nsh ? 15 + c : -1;
+    }
+    default:  // hidden-to-hidden layers: unit 16 (e >> 2) + 4 g + (e & 3)
+      return 16 * (e >> 2) + 4 * g + (e & 3);
+  }
+}
+
+uint16_t f16_bits(float f) {
+  _Float16 h = (_Float16)f;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+void arrange_weights(const float* W, int L, int nsh, std::vector<float>& w32, std::vector<uint16_t>& w16,
+                     std::vector<uint16_t>& wbf, std::vector<float>& bias) {
+  const int din = 2 * L, cin = 15 + nsh;
+  // offsets into the concatenated host weights
+  const float* W1 = W;
+  const float* b1 = W1 + din * 64;
+  const float* W2 = b1 + 64;
+  const float* b2 = W2 + 64 * 16;
+  const float* W3 = b2 + 16;
+  const float* b3 = W3 + cin * 64;
+  const float* W4 = b3 + 64;
+  const float* b4 = W4 + 64 * 64;
+  const float* W5 = b4 + 64;
+  const float* b5 = W5 + 64 * 3;
+  struct Layer { const float* w; int n_in, n_out, n_ot, n_k, off; };
+  const Layer layers[5] = {{W1, din, 64, 4, 8, kW32_D1}, {W2, 64, 16, 1, 16, kW32_D2},
+                           {W3, cin, 64, 4, 8, kW32_C1}, {W4, 64, 64, 4, 16, kW32_C2},
+                           {W5, 64, 3, 1, 16, kW32_C3}};
+  w32.assign(kW32Total, 0.0f);
+  w16.assign(kW16Total, 0);
+  wbf.assign(kW16Total, 0);
+  for (int li = 0; li < 5; ++li) {
+    const Layer& Ly = layers[li];
+    for (int ot = 0; ot < Ly.n_ot; ++ot)
+      for (int s = 0; s < Ly.n_k; ++s)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int g = lane >> 4, out = 16 * ot + (lane & 15);
+          const int in = in_index(li, g, s, L, nsh);
+          const float v = (in >= 0 && in < Ly.n_in && out < Ly.n_out) ? Ly.w[in * Ly.n_out + out] : 0.0f;
+          w32[Ly.off + ((ot * (Ly.n_k / 4) + s / 4) * 64 + lane) * 4 + (s % 4)] = v;
+          const int s2 = s >> 3, j = s & 7;
+          const size_t o16 = Ly.off + ((size_t)(ot * (Ly.n_k / 8) + s2) * 64 + lane) * 8 + j;
+          w16[o16] = f16_bits(v);
+          wbf[o16] = bf16_bits(v);
+        }
+  }
+  bias.assign(kBiasTotal, 0.0f);
+  for (int i = 0; i < 64; ++i) {
+    bias[kB1 + i] = b1[i];
+    bias[kB3 + i] = b3[i];
+    bias[kB4 + i] = b4[i];
+  }
+  for (int i = 0; i < 16; ++i) bias[kB2 + i] = b2[i];
+  for (int i = 0; i < 3; ++i) bias[kB5 + i] = b5[i];
+}
+
+uint64_t weight_count(int L, int nsh) {
+  const uint64_t din = 2 * L, cin = 15 + nsh;
+  return din * 64 + 64 + 64 * 16 + 16 + cin * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3;
+}
+
+vrn_status validate_desc(const vrn_field_desc* d) {
+  if (!d) return fail(VRN_ERR_INVALID_ARG, "field descriptor is NULL");
+  if (d->n_feat != 2) return fail(VRN_ERR_UNSUPPORTED, "only F = 2 features per entry are supported");
+  if (d->n_levels < 1 || d->n_levels > (uint32_t)kMaxLevels)
+    return fail(VRN_ERR_UNSUPPORTED, "n_levels must be 1..16");
+  if (d->log2_T < 4 || d->log2_T > 24) return fail(VRN_ERR_UNSUPPORTED, "log2_T must be 4..24");
+  if (!d->level_res || !d->tables || !d->weights || !d->occ_bits)
+    return fail(VRN_ERR_INVALID_ARG, "NULL level_res / tables / weights / occ_bits");
+  if (d->table_dtype != VRN_F32 && d->table_dtype != VRN_F16)
+    return fail(VRN_ERR_UNSUPPORTED, "table_dtype must be VRN_F32 or VRN_F16");
+  if (d->mlp_in != 2 * d->n_levels) return fail(VRN_ERR_INVALID_ARG, "mlp_in must equal 2 * n_levels");
+  if (d->mlp_hidden != 64) return fail(VRN_ERR_UNSUPPORTED, "mlp_hidden must be 64");
+  if (d->geo_out != 16) return fail(VRN_ERR_UNSUPPORTED, "geo_out must be 16");
+  if (d->sh_bands < 1 || d->sh_bands > 4) return fail(VRN_ERR_UNSUPPORTED, "sh_bands must be 1..4");
+  if (d->occ_res < 1 || d->occ_res > 1024) return fail(VRN_ERR_UNSUPPORTED, "occ_res must be 1..1024");
+  for (uint32_t l = 0; l < d->n_levels; ++l)
+    if (d->level_res[l] < 1 || d->level_res[l] > (1u << 20))
+      return fail(VRN_ERR_INVALID_ARG, "level_res must be 1..2^20");
+  for (int a = 0; a < 3; ++a)
+    if (!finite(d->aabb_min[a])) return fail(VRN_ERR_INVALID_ARG, "aabb_min not finite");
+  if (!finite(d->extent) || !(d->extent > 0.0f)) return fail(VRN_ERR_INVALID_ARG, "extent must be > 0");
+  if (!finite(d->dt) || !(d->dt > 0.0f)) return fail(VRN_ERR_INVALID_ARG, "dt must be > 0");
+  if (d->max_samples < 1) return fail(VRN_ERR_INVALID_ARG, "max_samples must be >= 1");
+  if (!finite(d->t_min) || d->t_min < 0.0f || d->t_min >= 1.0f)
+    return fail(VRN_ERR_INVALID_ARG, "t_min must be in [0, 1)");
+  if (d->lod_enable) {
+    if (!finite(d->base_res) || !(d->base_res > 0.0f)) return fail(VRN_ERR_INVALID_ARG, "base_res must be > 0");
+    if (!finite(d->growth) || !(d->growth > 1.0f)) return fail(VRN_ERR_INVALID_ARG, "growth must be > 1");
+    if (!finite(d->lod_bias)) return fail(VRN_ERR_INVALID_ARG, "lod_bias not finite");
+    if (!finite(d->lod_radius_scale) || !(d->lod_radius_scale > 0.0f))
+      return fail(VRN_ERR_INVALID_ARG, "lod_radius_scale must be > 0");
+  }
+  return VRN_OK;
+}
+
+vrn_status check_cams(const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H) {
+  if (!cams) return fail(VRN_ERR_INVALID_ARG, "cameras are NULL");
+  if (n_cams < 1 || n_cams > (uint32_t)kMaxCams) return fail(VRN_ERR_INVALID_ARG, "n_cams must be 1..16");
+  if (W < 1 || H < 1 || W > 16384 || H > 16384) return fail(VRN_ERR_INVALID_ARG, "W and H must be 1..16384");
+  if ((uint64_t)n_cams * W * H > (1ull << 31)) return fail(VRN_ERR_INVALID_ARG, "too many pixels in one call");
+  for (uint32_t c = 0; c < n_cams; ++c) {
+    const vrn_camera& k = cams[c];
+    for (int i = 0; i < 12; ++i)
+      if (!finite(k.c2w[i])) return fail(VRN_ERR_INVALID_ARG, "camera pose is not finite");
+    if (!finite(k.fx) || !finite(k.fy) || !finite(k.cx) || !finite(k.cy) || !(k.fx > 0.0f) || !(k.fy > 0.0f))
+      return fail(VRN_ERR_INVALID_ARG, "camera intrinsics must be finite with fx, fy > 0");
+    const float* R = k.c2w;
+    const double det = (double)R[0] * ((double)R[5] * R[10] - (double)R[6] * R[9]) -
+                       (double)R[1] * ((double)R[4] * R[10] - (double)R[6] * R[8]) +
+                       (double)R[2] * ((double)R[4] * R[9] - (double)R[5] * R[8]);
+    if (!(std::fabs(det) > 1e-6)) return fail(VRN_ERR_INVALID_ARG, "camera rotation is degenerate");
+    if (!(k.row_begin < k.row_end) || k.row_end > H)
+      return fail(VRN_ERR_INVALID_ARG, "camera rows must satisfy row_begin < row_end <= H");
+  }
+  return VRN_OK;
+}
+
+Field* find_field(vrn_ctx* ctx, vrn_field_id id) {
+  auto it = ctx->fields.find(id);
+  return it == ctx->fields.end() ? nullptr : it->second;
+}
+
+template <typename T>
+hipError_t upload(Field* f, const T* host, size_t count, T** out) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16));
+  if (e != hipSuccess) return e;
+  f->allocs.push_back(p);
+  f->bytes += count * sizeof(T);
+  e = hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice);
+  *out = static_cast<T*>(p);
+  return e;
+}
+
+void free_field(Field* f) {
+  for (hipEvent_t ev : f->events) hipEventDestroy(ev);
+  for (void* p : f->allocs) hipFree(p);
+  delete f;
+}
+
+void track(Field* f, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  hipEvent_t ev = nullptr;
+  for (hipEvent_t e : f->events)
+    if (hipEventQuery(e) == hipSuccess) {
+      ev = e;
+      break;
+    }
+  if (!ev) {
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
+    f->events.push_back(ev);
+  }
+  hipEventRecord(ev, s);
+}
+
+vrn_status check_opts(const vrn_render_opts* opts) {
+  if (opts && opts->compute != VRN_F32 && opts->compute != VRN_F16 && opts->compute != VRN_BF16)
+    return fail(VRN_ERR_INVALID_ARG, "opts.compute must be VRN_F32, VRN_F16 or VRN_BF16");
+  return VRN_OK;
+}
+
+vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t n_cams, uint32_t W,
+                     uint32_t H, const vrn_render_opts* opts, float* d_rgba, uint32_t* d_nsamples, void* ws,
+                     hipStream_t s) {
+  RenderArgs a{};
+  a.F = f->dev;
+  a.cams = d_cams;
+  a.n_cams = n_cams;
+  a.W = W;
+  a.H = H;
+  a.rgba = d_rgba;
+  a.nsamples = d_nsamples;
+  a.ws = static_cast<uint8_t*>(ws);
+  a.linear_hdr = opts ? opts->output_linear_hdr : 0;
+  a.budget = (opts && opts->march_budget) ? opts->march_budget : 64u;
+  const int compute = opts ? (int)opts->compute : 0;
+  const uint64_t rays = (uint64_t)n_cams * W * H;
+  const uint64_t want = (rays + kBlock - 1) / kBlock;
+  const uint64_t cap = (uint64_t)ctx->n_cu * render_blocks_per_cu(f->dev.table_f16, compute);
+  const int grid = (int)std::max<uint64_t>(1, std::min(want, cap));
+  hipError_t e = launch_render(a, compute, grid, s);
+  if (e != hipSuccess) return hip_fail(e, "render launch");
+  track(f, s);
+  return VRN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vrn_last_error(void) { return g_err.c_str(); }
+
+vrn_status vrn_create(int device, uint64_t hbm_budget_bytes, vrn_ctx** out) {
+  if (!out) return fail(VRN_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(VRN_ERR_DEVICE, "no HIP device available");
+  if (device < 0 || device >= n) return fail(VRN_ERR_DEVICE, "device ordinal out of range");
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  vrn_ctx* ctx = new vrn_ctx();
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  ctx->n_cu = prop.multiProcessorCount;
+  if ((e = hipMalloc(&ctx->ws, kWsBytes)) != hipSuccess) {
+    delete ctx;
+    return fail(VRN_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+  }
+  if ((e = hipMemset(ctx->ws, 0, kWsBytes)) != hipSuccess) {
+    hipFree(ctx->ws);
+    delete ctx;
+    return hip_fail(e, "workspace init");
+  }
+  *out = ctx;
+  return VRN_OK;
+}
+
+void vrn_destroy(vrn_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto& kv : ctx->fields) free_field(kv.second);
+  if (ctx->ws) hipFree(ctx->ws);
+  delete ctx;
+}
+
+vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* out) {
+  vrn_status st = validate_desc(d);
+  if (st != VRN_OK) return st;
+  if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  const uint32_t L = d->n_levels, G = d->occ_res, nsh = d->sh_bands * d->sh_bands;
+  const uint64_t T = 1ull << d->log2_T;
+  const uint64_t n_tab = (uint64_t)L * T * 2;
+  // finite tables and weights (LOD-skipped levels count as zeros only if finite)
+  if (d->table_dtype == VRN_F32) {
+    const float* t = static_cast<const float*>(d->tables);
+    for (uint64_t i = 0; i < n_tab; ++i)
+      if (!finite(t[i])) return fail(VRN_ERR_INVALID_ARG, "hash tables contain non-finite values");
+  } else {
+    const uint16_t* t = static_cast<const uint16_t*>(d->tables);
+    for (uint64_t i = 0; i < n_tab; ++i)
+      if ((t[i] & 0x7C00u) == 0x7C00u) return fail(VRN_ERR_INVALID_ARG, "hash tables contain non-finite values");
+  }
+  const uint64_t nw = weight_count((int)L, (int)nsh);
+  for (uint64_t i = 0; i < nw; ++i)
+    if (!finite(d->weights[i])) return fail(VRN_ERR_INVALID_ARG, "MLP weights contain non-finite values");
+
+  // coarse occupancy: OR over blocks of 2^bshift cells per axis
+  const uint32_t bshift = G >= 128 ? 3u : (G >= 16 ? 2u : 0u);
+  const uint32_t Gc = (G + (1u << bshift) - 1) >> bshift;
+  const uint64_t n_fine = (uint64_t)G * G * G, n_words = (n_fine + 31) / 32;
+  std::vector<uint32_t> coarse(((uint64_t)Gc * Gc * Gc + 31) / 32, 0u);
+  for (uint64_t w = 0; w < n_words; ++w) {
+    uint32_t word = d->occ_bits[w];
+    while (word) {
+      const int b = __builtin_ctz(word);
+      word &= word - 1;
+      const uint64_t i = w * 32 + (uint64_t)b;
+      if (i >= n_fine) break;
+      const uint32_t x = (uint32_t)(i % G), y = (uint32_t)((i / G) % G), z = (uint32_t)(i / ((uint64_t)G * G));
+      const uint64_t ci = (x >> bshift) + (uint64_t)Gc * ((y >> bshift) + (uint64_t)Gc * (z >> bshift));
+      coarse[ci >> 5] |= 1u << (ci & 31);
+    }
+  }
+  std::vector<float> w32, bias;
+  std::vector<uint16_t> w16, wbf;
+  arrange_weights(d->weights, (int)L, (int)nsh, w32, w16, wbf, bias);
+  std::vector<LevelDev> lv(L);
+  for (uint32_t l = 0; l < L; ++l) {
+    const uint64_t N = d->level_res[l], s = N + 1;
+    LevelDev& P = lv[l];
+    P.N = (uint32_t)N;
+    P.dense = (s * s * s <= T) ? 1u : 0u;
+    P.mx = P.dense ? 1u : d->hash_primes[0];
+    P.my = P.dense ? (uint32_t)s : d->hash_primes[1];
+    P.mz = P.dense ? (uint32_t)(s * s) : d->hash_primes[2];
+    const double S = (double)N / (double)d->extent;
+    P.s_hi = (float)S;
+    P.s_lo = (float)(S - (double)P.s_hi);
+    P.pad = 0;
+  }
+  const uint64_t tab_bytes = n_tab * (d->table_dtype == VRN_F16 ? 2 : 4);
+  const uint64_t need = tab_bytes + n_words * 4 + coarse.size() * 4 + (w32.size() + bias.size()) * 4 +
+                        (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev);
+  if (ctx->budget && ctx->used + need > ctx->budget)
+    return fail(VRN_ERR_BUDGET, "loading the field would exceed the HBM budget");
+
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  Field* f = new Field();
+  FieldDev& F = f->dev;
+  uint8_t* tab = nullptr;
+  LevelDev* dlv = nullptr;
+  uint32_t *docc = nullptr, *dco = nullptr;
+  float *dw32 = nullptr, *dbias = nullptr;
+  uint16_t *dw16 = nullptr, *dwbf = nullptr;
+  if ((e = upload(f, static_cast<const uint8_t*>(d->tables), tab_bytes, &tab)) ||
+      (e = upload(f, lv.data(), lv.size(), &dlv)) || (e = upload(f, d->occ_bits, n_words, &docc)) ||
+      (e = upload(f, coarse.data(), coarse.size(), &dco)) || (e = upload(f, w32.data(), w32.size(), &dw32)) ||
+      (e = upload(f, w16.data(), w16.size(), &dw16)) || (e = upload(f, wbf.data(), wbf.size(), &dwbf)) ||
+      (e = upload(f, bias.data(), bias.size(), &dbias))) {
+    free_field(f);
+    return e == hipErrorOutOfMemory ? fail(VRN_ERR_OUT_OF_MEMORY, "device allocation failed")
+                                    : hip_fail(e, "field upload");
+  }
+  F.tables = tab;
+  F.levels = dlv;
+  F.occ = docc;
+  F.occ_coarse = dco;
+  F.w32 = dw32;
+  F.w16 = dw16;
+  F.wbf = dwbf;
+  F.bias = dbias;
+  F.L = L;
+  F.log2T = d->log2_T;
+  F.Tmask = (uint32_t)(T - 1);
+  F.table_f16 = d->table_dtype == VRN_F16;
+  F.G = G;
+  F.Gc = Gc;
+  F.bshift = bshift;
+  F.nsh = nsh;
+  for (int a = 0; a < 3; ++a) F.amin[a] = d->aabb_min[a];
+  F.cs = (float)((double)G / (double)d->extent);
+  F.dt = d->dt;
+  F.t_min = d->t_min;
+  F.extent = d->extent;
+  F.max_samples = d->max_samples;
+  F.lod = d->lod_enable ? 1 : 0;
+  F.inv_ln_f = d->lod_enable ? (float)(1.0 / std::log((double)d->growth)) : 0.0f;
+  F.lod_c = d->lod_enable ? (float)std::log(2.0 * (double)d->base_res / (double)d->extent) : 0.0f;
+  F.lod_bias = d->lod_bias;
+  F.lod_radius_scale = d->lod_enable ? d->lod_radius_scale : 1.0f;
+  F.d1_ksteps = L > 8 ? 8u : 4u;
+  F.c1_ksteps = 8u;
+  const vrn_field_id id = ctx->next_id++;
+  ctx->fields[id] = f;
+  ctx->used += f->bytes;
+  *out = id;
+  return VRN_OK;
+}
+
+vrn_status vrn_unload_field(vrn_ctx* ctx, vrn_field_id field) {
+  if (!ctx) return fail(VRN_ERR_INVALID_ARG, "ctx is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  hipSetDevice(ctx->device);
+  for (hipEvent_t ev : f->events)
+    if (hipEventQuery(ev) == hipErrorNotReady) return fail(VRN_ERR_BUSY, "field has renders in flight");
+  ctx->used -= f->bytes;
+  ctx->fields.erase(field);
+  free_field(f);
+  return VRN_OK;
+}
+
+vrn_status vrn_field_bytes(vrn_ctx* ctx, vrn_field_id field, uint64_t* out) {
+  if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  *out = f->bytes;
+  return VRN_OK;
+}
+
+vrn_status vrn_workspace_bytes(vrn_ctx* ctx, uint64_t* out) {
+  if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
+  *out = kWsBytes;
+  return VRN_OK;
+}
+
+vrn_status vrn_workspace_init(vrn_ctx* ctx, void* ws, uint64_t bytes, void* stream) {
+  if (!ctx || !ws) return fail(VRN_ERR_INVALID_ARG, "ctx or workspace is NULL");
+  if (bytes < (uint64_t)kWsBytes) return fail(VRN_ERR_INVALID_ARG, "workspace too small");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hipSetDevice(ctx->device);
+  hipError_t e = launch_zero(ws, kWsBytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VRN_OK : hip_fail(e, "workspace init");
+}
+
+vrn_status vrn_check_cameras(const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H) {
+  return check_cams(cams, n_cams, W, H);
+}
+
+static vrn_status render_common(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, bool cams_dev,
+                                uint32_t n_cams, uint32_t W, uint32_t H, const vrn_render_opts* opts,
+                                float* d_rgba, uint32_t* d_nsamples, void* ws, uint64_t ws_bytes,
+                                void* stream) {
+  if (!cams) return fail(VRN_ERR_INVALID_ARG, "cameras are NULL");
+  vrn_status st = cams_dev ? VRN_OK : check_cams(cams, n_cams, W, H);
+  if (st != VRN_OK) return st;
+  if (!ctx) return fail(VRN_ERR_INVALID_ARG, "ctx is NULL");
+  if (!d_rgba) return fail(VRN_ERR_INVALID_ARG, "d_rgba is NULL");
+  if (cams_dev && (n_cams < 1 || n_cams > (uint32_t)kMaxCams || W < 1 || H < 1 || W > 16384 || H > 16384 ||
+                   (uint64_t)n_cams * W * H > (1ull << 31)))
+    return fail(VRN_ERR_INVALID_ARG, "n_cams must be 1..16 and W, H 1..16384");
+  if ((st = check_opts(opts)) != VRN_OK) return st;
+  if (ws && ws_bytes < (uint64_t)kWsBytes) return fail(VRN_ERR_INVALID_ARG, "workspace too small");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  void* w = ws ? ws : ctx->ws;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const vrn_camera* d_cams = cams;
+  if (!cams_dev) {
+    uint8_t* slot = static_cast<uint8_t*>(w) + kWsCams;
+    e = hipMemcpyAsync(slot, cams, n_cams * sizeof(vrn_camera), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "camera upload");
+    d_cams = reinterpret_cast<const vrn_camera*>(slot);
+  }
+  return do_render(ctx, f, d_cams, n_cams, W, H, opts, d_rgba, d_nsamples, w, s);
+}
+
+vrn_status vrn_render(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, uint32_t n_cams, uint32_t W,
+                      uint32_t H, const vrn_render_opts* opts, float* d_rgba, uint32_t* d_nsamples,
+                      void* d_workspace, uint64_t workspace_bytes, void* hip_stream) {
+  return render_common(ctx, field, cams, false, n_cams, W, H, opts, d_rgba, d_nsamples, d_workspace,
+                       workspace_bytes, hip_stream);
+}
+
+vrn_status vrn_render_device_cams(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* d_cams, uint32_t n_cams,
+                                  uint32_t W, uint32_t H, const vrn_render_opts* opts, float* d_rgba,
+                                  uint32_t* d_nsamples, void* d_workspace, uint64_t workspace_bytes,
+                                  void* hip_stream) {
+  return render_common(ctx, field, d_cams, true, n_cams, W, H, opts, d_rgba, d_nsamples, d_workspace,
+                       workspace_bytes, hip_stream);
+}
+
+vrn_status vrn_read_stats(vrn_ctx* ctx, const void* ws, vrn_stats* out, void* stream) {
+  if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hipSetDevice(ctx->device);
+  const uint8_t* w = static_cast<const uint8_t*>(ws ? ws : ctx->ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint64_t v[4];
+  hipError_t e = hipMemcpyAsync(v, w + kWsStats, sizeof(v), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "stats read");
+  out->rays = v[0];
+  out->samples = v[1];
+  out->level_fetches = v[2];
+  out->march_steps = v[3];
+  return VRN_OK;
+}
+
+vrn_status vrn_rays(vrn_ctx* ctx, const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H,
+                    float scale, float* d_o, float* d_d, float* d_r, void* stream) {
+  if (!ctx || !d_o || !d_d || !d_r) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
+  vrn_status st = check_cams(cams, n_cams, W, H);
+  if (st != VRN_OK) return st;
+  if (!finite(scale) || !(scale > 0.0f)) return fail(VRN_ERR_INVALID_ARG, "scale must be > 0");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* slot = static_cast<uint8_t*>(ctx->ws) + kWsCams;
+  hipError_t e = hipMemcpyAsync(slot, cams, n_cams * sizeof(vrn_camera), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_rays(reinterpret_cast<const vrn_camera*>(slot), n_cams, W, H, scale, d_o, d_d, d_r, s);
+  return e == hipSuccess ? VRN_OK : hip_fail(e, "rays");
+}
+
+vrn_status vrn_march(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, uint32_t n_cams, uint32_t W,
+                     uint32_t H, uint32_t* d_klist, uint32_t max_k, uint32_t* d_count, void* stream) {
+  if (!ctx || !d_count || (max_k > 0 && !d_klist)) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
+  vrn_status st = check_cams(cams, n_cams, W, H);
+  if (st != VRN_OK) return st;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* slot = static_cast<uint8_t*>(ctx->ws) + kWsCams;
+  hipError_t e = hipMemcpyAsync(slot, cams, n_cams * sizeof(vrn_camera), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_march(f->dev, reinterpret_cast<const vrn_camera*>(slot), n_cams, W, H, d_klist, max_k, d_count, s);
+  if (e != hipSuccess) return hip_fail(e, "march");
+  track(f, s);
+  return VRN_OK;
+}
+
+vrn_status vrn_encode(vrn_ctx* ctx, vrn_field_id field, const float* d_xyz, const float* d_t, const float* d_r,
+                      uint32_t n, float* d_feat, void* stream) {
+  if (!ctx || !d_xyz || !d_feat) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  if (f->dev.lod && (!d_t || !d_r)) return fail(VRN_ERR_INVALID_ARG, "LOD fields need d_t and d_r");
+  if (n == 0) return VRN_OK;
+  hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_encode(f->dev, d_xyz, d_t, d_r, n, d_feat, s);
+  if (e != hipSuccess) return hip_fail(e, "encode");
+  track(f, s);
+  return VRN_OK;
+}
+
+vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const float* d_dir, uint32_t n,
+                   vrn_dtype compute, float* d_sigma, float* d_rgb, void* stream) {
+  if (!ctx || !d_feat || !d_dir || !d_sigma || !d_rgb) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
+  if (compute != VRN_F32 && compute != VRN_F16 && compute != VRN_BF16)
+    return fail(VRN_ERR_INVALID_ARG, "compute must be VRN_F32, VRN_F16 or VRN_BF16");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  if (n == 0) return VRN_OK;
+  hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_mlp(f->dev, d_feat, d_dir, n, (int)compute, d_sigma, d_rgb, s);
+  if (e != hipSuccess) return hip_fail(e, "mlp");
+  track(f, s);
+  return VRN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,574 @@
+// Device functions of the renderer hot path (gfx950, wave64).
+//
+// Every function here is used both by the fused render kernel and by the
+// single-stage kernels behind vrn_rays / vrn_march / vrn_encode / vrn_mlp,
+// so stage parity tests exercise the exact code that renders frames.
+//
+// The translation unit is compiled with -ffp-contract=off: the ray and
+// lattice geometry below is the canonical FP32 operation sequence (each
+// product and sum rounded on its own), which is what makes occupancy cell
+// decisions reproducible bit for bit.  Fused multiply-adds are written
+// explicitly (fmaf) only where the math wants them.
+#pragma once
+
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace vrn {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ float shfl_f(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ int shfl_i(int v, int src) {
+  return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+
+// Position of the n-th (0-based) set bit of m; n < popcount(m).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = m & ((w == 64 ? 0ull : (1ull << w)) - 1ull);
+    const int c = __popcll(low);
+    if (n >= c) { n -= c; m >>= w; pos += w; } else { m = low; }
+  }
+  return pos;
+}
+
+// ---------------------------------------------------------------------------
+// Rays (Sec. 4.2.1 cone footprint; pinhole, OpenCV axes, pixel centres +0.5)
+// ---------------------------------------------------------------------------
+
+struct Ray {
+  float ox, oy, oz, dx, dy, dz;
+  float lr;      // ln(r) + ln(2 s / extent): log of the LOD footprint per unit t
+  float delta;   // block-skip margin in cell units (bounds FP32 rounding of q)
+  int k, k_hi;   // lattice cursor and last lattice index worth testing
+};
+
+// Canonical FP32 direction: a = ((i + .5) - cx) / fx, b = ((j + .5) - cy) / fy,
+// w = (R[:,0] a + R[:,1] b) + R[:,2], d = w / sqrt((wx wx + wy wy) + wz wz).
+__device__ __forceinline__ void canonical_ray(const vrn_camera& c, uint32_t col, uint32_t row,
+                                              float w[3], float& n, float d[3]) {
+  const float a = (((float)col + 0.5f) - c.cx) / c.fx;
+  const float b = (((float)row + 0.5f) - c.cy) / c.fy;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) w[r] = (c.c2w[4 * r] * a + c.c2w[4 * r + 1] * b) + c.c2w[4 * r + 2];
+  n = sqrtf((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) d[r] = w[r] / n;
+}
+
+// Base radius at unit distance: chord between the unit directions of this
+// pixel and its right neighbour, 2 sin(theta / 2), evaluated without
+// cancellation: sin(theta) = |w x v| / (|w| |w + v|) with v = R[:,0] / fx.
+__device__ __forceinline__ float cone_pitch(const vrn_camera& c, const float w[3], float n, float scale) {
+  const float v[3] = {c.c2w[0] / c.fx, c.c2w[4] / c.fx, c.c2w[8] / c.fx};
+  const float e[3] = {w[0] + v[0], w[1] + v[1], w[2] + v[2]};
+  const float cx = w[1] * v[2] - w[2] * v[1];
+  const float cy = w[2] * v[0] - w[0] * v[2];
+  const float cz = w[0] * v[1] - w[1] * v[0];
+  const float ne = sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  const float sn = sqrtf(cx * cx + cy * cy + cz * cz) / (n * ne);
+  const float cs = (w[0] * e[0] + w[1] * e[1] + w[2] * e[2]) / (n * ne);
+  return scale * sn / sqrtf(0.5f * (1.0f + cs));
+}
+
+// Lattice range [k_lo, k_hi] from an FP32 slab test padded by two steps on
+// each side; the canonical per-sample test alone decides membership.
+__device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
+  const float o[3] = {r.ox, r.oy, r.oz};
+  const float d[3] = {r.dx, r.dy, r.dz};
+  float tn = 0.0f, tf = 3.0e38f;
+  bool miss = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = F.amin[a], hi = F.amin[a] + F.extent;
+    if (d[a] != 0.0f) {
+      const float t1 = (lo - o[a]) / d[a], t2 = (hi - o[a]) / d[a];
+      tn = fmaxf(tn, fminf(t1, t2));
+      tf = fminf(tf, fmaxf(t1, t2));
+    } else if (o[a] < lo || o[a] > hi) {
+      miss = true;
+    }
+  }
+  const float kmax = 16777000.0f;  // keep k < 2^24 (k + 0.5 exact in FP32)
+  const float klo = floorf(tn / F.dt - 0.5f) - 2.0f;
+  const float khi = ceilf(fminf(tf / F.dt, kmax) - 0.5f) + 2.0f;
+  if (miss || !(tf >= tn - 2.0f * F.dt) || klo > kmax) {
+    r.k = 0;
+    r.k_hi = -1;
+  } else {
+    r.k = (int)fmaxf(klo, 0.0f);
+    r.k_hi = (int)fminf(khi, kmax);
+  }
+  const float M = fmaxf(fabsf(o[0]), fmaxf(fabsf(o[1]), fabsf(o[2]))) + fminf(tf, kmax * F.dt) +
+                  fmaxf(fabsf(F.amin[0]), fmaxf(fabsf(F.amin[1]), fabsf(F.amin[2])));
+  r.delta = ldexpf(F.cs * M + (float)F.G + 1.0f, -20);
+}
+
+__device__ __forceinline__ void setup_ray(const FieldDev& F, const vrn_camera& c, uint32_t col,
+                                          uint32_t row, Ray& r) {
+  float w[3], n, d[3];
+  canonical_ray(c, col, row, w, n, d);
+  r.ox = c.c2w[3];
+  r.oy = c.c2w[7];
+  r.oz = c.c2w[11];
+  r.dx = d[0];
+  r.dy = d[1];
+  r.dz = d[2];
+  r.lr = F.lod ? logf(cone_pitch(c, w, n, F.lod_radius_scale)) + F.lod_c : 0.0f;
+  lattice_range(F, r);
+}
+
+// ---------------------------------------------------------------------------
+// Occupancy march (Sec. 4.3)
+// ---------------------------------------------------------------------------
+
+// Canonical lattice sample k: t = (k + .5) dt, x = o + t d, q = (x - amin) cs.
+__device__ __forceinline__ void lattice_q(const FieldDev& F, const Ray& r, int k, float& t, float x[3],
+                                          float q[3]) {
+  t = ((float)k + 0.5f) * F.dt;
+  x[0] = r.ox + t * r.dx;
+  x[1] = r.oy + t * r.dy;
+  x[2] = r.oz + t * r.dz;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q[a] = (x[a] - F.amin[a]) * F.cs;
+}
+
+__device__ __forceinline__ int cell_of(float q, int G) {
+  return (int)floorf(fminf(fmaxf(q, -1.0f), (float)G));
+}
+
+__device__ __forceinline__ bool bit_set(const uint32_t* bits, uint32_t idx) {
+  return (bits[idx >> 5] >> (idx & 31u)) & 1u;
+}
+
+// Advance to the next evaluated sample within `budget` lattice tests.
+// Returns 1 (sample found; t, x are its canonical values), 0 (budget used
+// up) or 2 (ray exhausted).  Empty space is skipped a coarse block at a time
+// when the current sample and the landing sample both lie in the same empty
+// block shrunk by delta: by convexity every lattice sample in between then
+// lies in that block too (delta >= twice the FP32 error of q), so the skip
+// never passes a sample whose canonical cell is occupied.
+__device__ __forceinline__ int march_next(const FieldDev& F, Ray& r, uint32_t budget, uint32_t& steps,
+                                          float& st, float sx[3]) {
+  const int G = (int)F.G;
+  const float B = (float)(1u << F.bshift);
+  for (uint32_t it = 0; it < budget; ++it) {
+    if (r.k > r.k_hi) return 2;
+    ++steps;
+    float t, x[3], q[3];
+    lattice_q(F, r, r.k, t, x, q);
+    const int cx = cell_of(q[0], G), cy = cell_of(q[1], G), cz = cell_of(q[2], G);
+    bool skipped = false;
+    if ((unsigned)cx < (unsigned)G && (unsigned)cy < (unsigned)G && (unsigned)cz < (unsigned)G) {
+      const uint32_t idx = (uint32_t)cx + (uint32_t)G * ((uint32_t)cy + (uint32_t)G * (uint32_t)cz);
+      if (bit_set(F.occ, idx)) {
+        st = t;
+        sx[0] = x[0];
+        sx[1] = x[1];
+        sx[2] = x[2];
+        r.k++;
+        return 1;
+      }
+      const int bx = cx >> F.bshift, by = cy >> F.bshift, bz = cz >> F.bshift;
+      const uint32_t bidx = (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz);
+      if (!bit_set(F.occ_coarse, bidx)) {
+        const float lo[3] = {bx * B + r.delta, by * B + r.delta, bz * B + r.delta};
+        const float hi[3] = {(bx + 1) * B - r.delta, (by + 1) * B - r.delta, (bz + 1) * B - r.delta};
+        const bool in0 = q[0] >= lo[0] && q[0] <= hi[0] && q[1] >= lo[1] && q[1] <= hi[1] &&
+                         q[2] >= lo[2] && q[2] <= hi[2];
+        if (in0) {
+          const float o[3] = {r.ox, r.oy, r.oz};
+          const float d[3] = {r.dx, r.dy, r.dz};
+          float te = 3.0e38f;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float bq = signbit(d[a]) ? lo[a] : hi[a];
+            te = fminf(te, (bq / F.cs + F.amin[a] - o[a]) / d[a]);
+          }
+          const float kbf = fminf(floorf(te / F.dt - 0.5f), (float)r.k_hi);
+          if (kbf >= (float)r.k + 2.0f) {
+            int kb = (int)kbf;
+#pragma unroll
+            for (int tries = 0; tries < 2 && !skipped; ++tries, --kb) {
+              float t2, x2[3], q2[3];
+              lattice_q(F, r, kb, t2, x2, q2);
+              if (q2[0] >= lo[0] && q2[0] <= hi[0] && q2[1] >= lo[1] && q2[1] <= hi[1] &&
+                  q2[2] >= lo[2] && q2[2] <= hi[2]) {
+                r.k = kb + 1;
+                skipped = true;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (!skipped) r.k++;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Hash encoding with LOD (Sec. 4 after iNGP; Sec. 4.2.1 Eq. 3; App. D)
+// ---------------------------------------------------------------------------
+
+// Exact a - b as hi + lo (Knuth two-sum).
+__device__ __forceinline__ void two_diff(float a, float b, float& hi, float& lo) {
+  const float s = a - b;
+  const float ap = s + b;
+  const float bp = s - ap;
+  lo = (a - ap) + (-b - bp);
+  hi = s;
+}
+
+// Base lattice corner and fraction of p = u * S computed as a double-float
+// (u = uh + ul exact, S = s_hi + s_lo): the fraction is accurate to one
+// rounding even at 2e4-cell levels.
+__device__ __forceinline__ uint32_t base_corner(float uh, float ul, float shi, float slo, uint32_t N,
+                                                float& fr) {
+  const float ph = uh * shi;
+  const float pe = fmaf(uh, shi, -ph);
+  const float pl = pe + (uh * slo + ul * shi);
+  const float fi = fminf(fmaxf(floorf(ph), 0.0f), (float)(N - 1));
+  fr = (ph - fi) + pl;
+  return (uint32_t)fi;
+}
+
+// Lane (sample, level group g) encodes levels g, g+4, g+8, g+12 of one point.
+// Levels with LOD weight 0 are not fetched.  feat[2j + f] = level g + 4j,
+// feature f.
+template <bool TAB16>
+__device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* lv, const float x[3],
+                                             float lstar, bool active, int g, float feat[8],
+                                             uint32_t& fetches) {
+  float uh[3], ul[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) two_diff(x[a], F.amin[a], uh[a], ul[a]);
+  const uint32_t T = F.Tmask + 1u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    feat[2 * j] = 0.0f;
+    feat[2 * j + 1] = 0.0f;
+    const int lev = g + 4 * j;
+    if (!active || lev >= (int)F.L) continue;
+    const float w = F.lod ? fminf(fmaxf(lstar + 1.0f - (float)lev, 0.0f), 1.0f) : 1.0f;
+    if (!(w > 0.0f)) continue;
+    const LevelDev P = lv[lev];
+    float fr[3];
+    uint32_t i0[3];
+    i0[0] = base_corner(uh[0], ul[0], P.s_hi, P.s_lo, P.N, fr[0]);
+    i0[1] = base_corner(uh[1], ul[1], P.s_hi, P.s_lo, P.N, fr[1]);
+    i0[2] = base_corner(uh[2], ul[2], P.s_hi, P.s_lo, P.N, fr[2]);
+    const uint32_t ax0 = i0[0] * P.mx, ax1 = ax0 + P.mx;
+    const uint32_t ay0 = i0[1] * P.my, ay1 = ay0 + P.my;
+    const uint32_t az0 = i0[2] * P.mz, az1 = az0 + P.mz;
+    uint32_t idx[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t a = (c & 1) ? ax1 : ax0, b = (c & 2) ? ay1 : ay0, e = (c & 4) ? az1 : az0;
+      idx[c] = P.dense ? (a + b + e) : ((a ^ b ^ e) & F.Tmask);
+    }
+    float v0[8], v1[8];
+    if (TAB16) {
+      const uint32_t* tab = reinterpret_cast<const uint32_t*>(F.tables) + (size_t)lev * T;
+      uint32_t raw[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) raw[c] = tab[idx[c]];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        _Float16 h0, h1;
+        const uint16_t lo16 = (uint16_t)(raw[c] & 0xFFFFu), hi16 = (uint16_t)(raw[c] >> 16);
+        __builtin_memcpy(&h0, &lo16, 2);
+        __builtin_memcpy(&h1, &hi16, 2);
+        v0[c] = (float)h0;
+        v1[c] = (float)h1;
+      }
+    } else {
+      const float2* tab = reinterpret_cast<const float2*>(F.tables) + (size_t)lev * T;
+      float2 raw[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) raw[c] = tab[idx[c]];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        v0[c] = raw[c].x;
+        v1[c] = raw[c].y;
+      }
+    }
+    const float wx[2] = {1.0f - fr[0], fr[0]};
+    const float wy[2] = {1.0f - fr[1], fr[1]};
+    const float wz[2] = {1.0f - fr[2], fr[2]};
+    float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float wc = (wx[c & 1] * wy[(c >> 1) & 1]) * wz[c >> 2];
+      acc0 = fmaf(wc, v0[c], acc0);
+      acc1 = fmaf(wc, v1[c], acc1);
+    }
+    feat[2 * j] = w * acc0;
+    feat[2 * j + 1] = w * acc1;
+    ++fetches;
+  }
+}
+
+// Optimal LOD level L* = -log_f(2 s r_hat) + bias, clamped at 0 (Sec. 4.2.1-2),
+// with r_hat = t r / extent and lr = ln(r) + ln(2 s / extent).
+__device__ __forceinline__ float level_star(const FieldDev& F, float t, float lr) {
+  return fmaxf(-(logf(t) + lr) * F.inv_ln_f + F.lod_bias, 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Direction encoding: real SH, bands 0..3, no Condon-Shortley phase,
+// order (l, m = -l..l).  Constants from the closed-form polynomials.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void sh_basis16(float x, float y, float z, float s[16]) {
+  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
+  s[0] = 0.28209479177387814f;
+  s[1] = 0.4886025119029199f * y;
+  s[2] = 0.4886025119029199f * z;
+  s[3] = 0.4886025119029199f * x;
+  s[4] = 1.0925484305920792f * xy;
+  s[5] = 1.0925484305920792f * yz;
+  s[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+  s[7] = 1.0925484305920792f * xz;
+  s[8] = 0.5462742152960396f * (xx - yy);
+  s[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+  s[10] = 2.890611442640554f * xy * z;
+  s[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+  s[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+  s[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+  s[14] = 1.445305721320277f * z * (xx - yy);
+  s[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// The SH values lane group g feeds to the first color layer: c = g + 4 i.
+__device__ __forceinline__ void sh_select(const FieldDev& F, float x, float y, float z, int g, float out[4]) {
+  float s[16];
+  sh_basis16(x, y, z, s);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float v = g == 0 ? s[4 * i] : g == 1 ? s[4 * i + 1] : g == 2 ? s[4 * i + 2] : s[4 * i + 3];
+    out[i] = (uint32_t)(g + 4 * i) < F.nsh ? v : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MLPs on MFMA (Sec. 5: fused, in-register small MLPs; Sec. 6: 64 wide).
+//
+// One call evaluates 16 samples.  Every layer computes D^T = W^T X^T with
+// 16x16 output tiles: lane l holds output (4 (l >> 4) + r) of sample
+// (l & 15) in accumulator register r.  Because the MFMA contraction is
+// invariant under any permutation of k that A and B share, that accumulator
+// layout is used directly as the B operand of the next layer -- lane group
+// g = l >> 4 contributes hidden units {16 t + 4 g + r} -- and the host lays
+// the weight fragments out in the same order.  No activation ever leaves
+// the registers.  The first layer's B operand is the lane's own encoded
+// features (levels g + 4 j); the first color layer's is the lane's density
+// outputs 4 g + r (output 0, the density, meets zero weights) followed by
+// the SH values g + 4 i.
+// Result: lanes 0..15 hold o0 (density pre-activation) and the three color
+// logits of samples 0..15.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ v4f bias4(const float* sb, int base, int g) {
+  v4f b;
+  b[0] = sb[base + 4 * g + 0];
+  b[1] = sb[base + 4 * g + 1];
+  b[2] = sb[base + 4 * g + 2];
+  b[3] = sb[base + 4 * g + 3];
+  return b;
+}
+
+__device__ __forceinline__ v4f relu4(v4f v) {
+  v4f r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = fmaxf(v[i], 0.0f);
+  return r;
+}
+
+// FP32 path: v_mfma_f32_16x16x4_f32, weights as float4 = 4 consecutive k-steps.
+__device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, const float* __restrict__ sb,
+                                             uint32_t d1_groups, const float feat[8],
+                                             const float shs[4], int lane, float& o0, float lg[3]) {
+  const int g = lane >> 4;
+  v4f h[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) h[ot] = bias4(sb, kB1 + 16 * ot, g);
+  for (uint32_t s4 = 0; s4 < d1_groups; ++s4) {
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+      const float4 w = sw[kW32_D1 / 4 + (ot * 2 + s4) * 64 + lane];
+      h[ot] = mfma_f32(w.x, feat[4 * s4 + 0], h[ot]);
+      h[ot] = mfma_f32(w.y, feat[4 * s4 + 1], h[ot]);
+      h[ot] = mfma_f32(w.z, feat[4 * s4 + 2], h[ot]);
+      h[ot] = mfma_f32(w.w, feat[4 * s4 + 3], h[ot]);
+    }
+  }
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) h[ot] = relu4(h[ot]);
+  v4f o = bias4(sb, kB2, g);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const float4 w = sw[kW32_D2 / 4 + it * 64 + lane];
+    o = mfma_f32(w.x, h[it][0], o);
+    o = mfma_f32(w.y, h[it][1], o);
+    o = mfma_f32(w.z, h[it][2], o);
+    o = mfma_f32(w.w, h[it][3], o);
+  }
+  v4f c1[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    c1[ot] = bias4(sb, kB3 + 16 * ot, g);
+    const float4 w0 = sw[kW32_C1 / 4 + (ot * 2 + 0) * 64 + lane];
+    c1[ot] = mfma_f32(w0.x, o[0], c1[ot]);
+    c1[ot] = mfma_f32(w0.y, o[1], c1[ot]);
+    c1[ot] = mfma_f32(w0.z, o[2], c1[ot]);
+    c1[ot] = mfma_f32(w0.w, o[3], c1[ot]);
+    const float4 w1 = sw[kW32_C1 / 4 + (ot * 2 + 1) * 64 + lane];
+    c1[ot] = mfma_f32(w1.x, shs[0], c1[ot]);
+    c1[ot] = mfma_f32(w1.y, shs[1], c1[ot]);
+    c1[ot] = mfma_f32(w1.z, shs[2], c1[ot]);
+    c1[ot] = mfma_f32(w1.w, shs[3], c1[ot]);
+  }
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) c1[ot] = relu4(c1[ot]);
+  v4f c2[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    c2[ot] = bias4(sb, kB4 + 16 * ot, g);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const float4 w = sw[kW32_C2 / 4 + (ot * 4 + it) * 64 + lane];
+      c2[ot] = mfma_f32(w.x, c1[it][0], c2[ot]);
+      c2[ot] = mfma_f32(w.y, c1[it][1], c2[ot]);
+      c2[ot] = mfma_f32(w.z, c1[it][2], c2[ot]);
+      c2[ot] = mfma_f32(w.w, c1[it][3], c2[ot]);
+    }
+  }
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) c2[ot] = relu4(c2[ot]);
+  v4f c3 = bias4(sb, kB5, g);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const float4 w = sw[kW32_C3 / 4 + it * 64 + lane];
+    c3 = mfma_f32(w.x, c2[it][0], c3);
+    c3 = mfma_f32(w.y, c2[it][1], c3);
+    c3 = mfma_f32(w.z, c2[it][2], c3);
+    c3 = mfma_f32(w.w, c2[it][3], c3);
+  }
+  o0 = o[0];
+  lg[0] = c3[0];
+  lg[1] = c3[1];
+  lg[2] = c3[2];
+}
+
+// 16-bit paths: v_mfma_f32_16x16x32_{f16,bf16}; 8 k-values per lane per step.
+__device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <bool BF>
+struct Half8 {
+  typedef typename std::conditional<BF, v8bf, v8h>::type vec;
+  __device__ static __forceinline__ vec pack(const float* v) {
+    vec r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if constexpr (BF) {
+        const uint16_t b = bf16_bits_rne(v[i]);
+        __bf16 x;
+        __builtin_memcpy(&x, &b, 2);
+        r[i] = x;
+      } else {
+        r[i] = (_Float16)v[i];
+      }
+    }
+    return r;
+  }
+  __device__ static __forceinline__ v4f mfma(vec a, vec b, v4f c) {
+    if constexpr (BF) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <bool BF>
+__device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const float* __restrict__ sb,
+                                            const float feat[8], const float shs[4], int lane,
+                                            float& o0, float lg[3]) {
+  typedef Half8<BF> H;
+  typedef typename H::vec vec;
+  const int g = lane >> 4;
+  auto wfrag = [&](int off16, int idx) -> vec {
+    const uint4 u = sw[off16 / 8 + idx * 64 + lane];
+    vec v;
+    __builtin_memcpy(&v, &u, 16);
+    return v;
+  };
+  const vec xin = H::pack(feat);
+  v4f h[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) h[ot] = H::mfma(wfrag(kW16_D1, ot), xin, bias4(sb, kB1 + 16 * ot, g));
+  float hv[16];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(h[ot][r], 0.0f);
+  v4f o = bias4(sb, kB2, g);
+  o = H::mfma(wfrag(kW16_D2, 0), H::pack(hv), o);
+  o = H::mfma(wfrag(kW16_D2, 1), H::pack(hv + 8), o);
+  float cin[8] = {o[0], o[1], o[2], o[3], shs[0], shs[1], shs[2], shs[3]};
+  const vec cv = H::pack(cin);
+  v4f c1[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) c1[ot] = H::mfma(wfrag(kW16_C1, ot), cv, bias4(sb, kB3 + 16 * ot, g));
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(c1[ot][r], 0.0f);
+  const vec a0 = H::pack(hv), a1 = H::pack(hv + 8);
+  v4f c2[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    c2[ot] = bias4(sb, kB4 + 16 * ot, g);
+    c2[ot] = H::mfma(wfrag(kW16_C2, ot * 2 + 0), a0, c2[ot]);
+    c2[ot] = H::mfma(wfrag(kW16_C2, ot * 2 + 1), a1, c2[ot]);
+  }
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(c2[ot][r], 0.0f);
+  v4f c3 = bias4(sb, kB5, g);
+  c3 = H::mfma(wfrag(kW16_C3, 0), H::pack(hv), c3);
+  c3 = H::mfma(wfrag(kW16_C3, 1), H::pack(hv + 8), c3);
+  o0 = o[0];
+  lg[0] = c3[0];
+  lg[1] = c3[1];
+  lg[2] = c3[2];
+}
+
+// ---------------------------------------------------------------------------
+// PQ decode (Sec. 4.1, algebraic inverse of Eq. 1), linear 1 = 100 cd/m^2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float pq_to_linear(float e) {
+  const float m1 = 1305.0f / 8192.0f, m2 = 2523.0f / 32.0f;
+  const float c1 = 107.0f / 128.0f, c2 = 2413.0f / 128.0f, c3 = 2392.0f / 128.0f;
+  const float ep = powf(fmaxf(e, 0.0f), 1.0f / m2);
+  const float y = powf(fmaxf(ep - c1, 0.0f) / (c2 - c3 * ep), 1.0f / m1);
+  return 100.0f * y;
+}
+
+}  // namespace vrn

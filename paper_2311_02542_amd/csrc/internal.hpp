@@ -1,0 +1,87 @@
+// Internal host/device structures shared by the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vrn.h"
+
+namespace vrn {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCams = VRN_MAX_CAMS;
+constexpr int kQueues = 8;          // one ray queue per XCD
+constexpr int kTile = 8;            // rays are issued in 8x8 pixel tiles
+constexpr int kBlock = 256;         // threads per render block (4 waves)
+constexpr int kHidden = 64;
+
+// MFMA fragment layout of the MLP weights (see mlp_tile in device.hpp).
+// FP32: [layer][out_tile][kstep/4][lane][4]; FP16/BF16: [layer][out_tile][kstep][lane][8].
+constexpr int kW32_D1 = 0, kW32_D2 = 2048, kW32_C1 = 3072, kW32_C2 = 5120, kW32_C3 = 9216;
+constexpr int kW32Total = 10240;    // floats
+constexpr int kW16_D1 = 0, kW16_D2 = 2048, kW16_C1 = 3072, kW16_C2 = 5120, kW16_C3 = 9216;
+constexpr int kW16Total = 10240;    // 16-bit values
+// biases: b1[64] b2[16] b3[64] b4[64] b5[16 (3 used)]
+constexpr int kB1 = 0, kB2 = 64, kB3 = 80, kB4 = 144, kB5 = 208, kBiasTotal = 224;
+
+struct LevelDev {
+  uint32_t N;        // lattice resolution (N + 1 points per axis)
+  uint32_t dense;    // 1: index = x + y s + z s^2 with s = N + 1
+  uint32_t mx, my, mz;  // per-axis multipliers: (1, s, s^2) dense, hash primes otherwise
+  float s_hi, s_lo;  // N / extent as an unevaluated sum of two floats
+  uint32_t pad;
+};
+
+struct FieldDev {
+  const void* tables;        // [L][T][2] fp32 or fp16
+  const LevelDev* levels;    // [L]
+  const uint32_t* occ;       // G^3 bits
+  const uint32_t* occ_coarse;// Gc^3 bits, block = 2^bshift cells
+  const float* w32;          // kW32Total
+  const uint16_t* w16;       // kW16Total fp16 bits
+  const uint16_t* wbf;       // kW16Total bf16 bits
+  const float* bias;         // kBiasTotal
+  uint32_t L, log2T, Tmask, table_f16;
+  uint32_t G, Gc, bshift, nsh;
+  float amin[3], cs;         // cs = fp32(G / extent)
+  float dt, t_min, extent, inv_ln_f;
+  uint32_t max_samples;
+  int32_t lod;
+  float lod_c;               // ln(2 s / extent)
+  float lod_bias, lod_radius_scale;
+  uint32_t d1_ksteps;        // FP32 k-steps of the first density layer
+  uint32_t c1_ksteps;        // FP32 k-steps of the first color layer
+};
+
+// Workspace layout (bytes).  Counters are spaced 64 B apart.
+constexpr int kWsQueue = 0;        // kQueues x u32 at stride 16 u32
+constexpr int kWsDone = 512;       // u32 blocks-finished counter
+constexpr int kWsStats = 576;      // 4 x u64
+constexpr int kWsCams = 640;       // kMaxCams x vrn_camera
+constexpr int kWsBytes = 4096;
+
+struct RenderArgs {
+  FieldDev F;
+  const vrn_camera* cams;    // device
+  uint32_t n_cams, W, H;
+  float* rgba;               // [n_cams][H][W][4]
+  uint32_t* nsamples;        // nullable
+  uint8_t* ws;               // workspace
+  int32_t linear_hdr;
+  uint32_t budget;           // march steps per round
+};
+
+// launchers (kernels.hip)
+hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t s);
+int render_blocks_per_cu(int table_f16, int compute);
+hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
+hipError_t launch_rays(const vrn_camera* d_cams, uint32_t n_cams, uint32_t W, uint32_t H,
+                       float scale, float* o, float* d, float* r, hipStream_t s);
+hipError_t launch_march(const FieldDev& F, const vrn_camera* d_cams, uint32_t n_cams, uint32_t W,
+                        uint32_t H, uint32_t* klist, uint32_t max_k, uint32_t* count, hipStream_t s);
+hipError_t launch_encode(const FieldDev& F, const float* xyz, const float* t, const float* r,
+                         uint32_t n, float* feat, hipStream_t s);
+hipError_t launch_mlp(const FieldDev& F, const float* feat, const float* dir, uint32_t n,
+                      int compute, float* sigma, float* rgb, hipStream_t s);
+
+}  // namespace vrn

@@ -1,0 +1,124 @@
+"""Host-side tests of the C ABI: the library builds, loads and exports every
+symbol include/vrn.h declares; argument validation runs on the host before
+any device work (so these paths are testable without a GPU)."""
+import ctypes
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2311_02542_amd import capi, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(capi.LIB_PATH):
+        from paper_2311_02542_amd import build
+        build.build()
+    return capi.load_library()
+
+
+def test_exports_every_header_symbol(lib):
+    names = capi.header_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_create_without_device_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ctx = ctypes.c_void_p()
+    assert lib.vrn_create(0, 0, ctypes.byref(ctx)) == capi.VRN_ERR_DEVICE
+    assert "device" in lib.vrn_last_error().decode()
+    assert lib.vrn_create(0, 0, None) == capi.VRN_ERR_INVALID_ARG
+
+
+def _cam(**kw):
+    c = synth.cameras_c1(1)[0]
+    c = dict(c)
+    c.update(kw)
+    return c
+
+
+def test_camera_validation(lib):
+    assert capi.vrn_check_cameras([_cam()], 64, 64) == capi.VRN_OK
+    bad = _cam()
+    bad["c2w"] = bad["c2w"].copy()
+    bad["c2w"][0, 0] = np.nan
+    assert capi.vrn_check_cameras([bad], 64, 64) == capi.VRN_ERR_INVALID_ARG
+    deg = _cam()
+    deg["c2w"] = deg["c2w"].copy()
+    deg["c2w"][:, 1] = deg["c2w"][:, 0]          # degenerate rotation
+    assert capi.vrn_check_cameras([deg], 64, 64) == capi.VRN_ERR_INVALID_ARG
+    assert capi.vrn_check_cameras([_cam(fx=np.float32(0))], 64, 64) == capi.VRN_ERR_INVALID_ARG
+    assert capi.vrn_check_cameras([_cam(row_begin=10, row_end=10)], 64, 64) == capi.VRN_ERR_INVALID_ARG
+    assert capi.vrn_check_cameras([_cam(row_begin=0, row_end=65)], 64, 64) == capi.VRN_ERR_INVALID_ARG
+    assert capi.vrn_check_cameras([_cam()], 0, 64) == capi.VRN_ERR_INVALID_ARG
+    assert capi.vrn_check_cameras([_cam()] * 17, 64, 64) == capi.VRN_ERR_INVALID_ARG
+
+
+def test_render_rejects_bad_cameras_before_device_work(lib):
+    bad = _cam()
+    bad["c2w"] = bad["c2w"].copy()
+    bad["c2w"][1, 3] = np.inf
+    arr = capi.make_cameras([bad], 64)
+    st = lib.vrn_render(None, 1, arr, 1, 64, 64, None, None, None, None, 0, None)
+    assert st == capi.VRN_ERR_INVALID_ARG
+    arr = capi.make_cameras([_cam()], 64)
+    st = lib.vrn_render(None, 1, arr, 1, 64, 64, None, None, None, None, 0, None)
+    assert st == capi.VRN_ERR_INVALID_ARG      # NULL context
+
+
+def _desc_status(lib, field, **over):
+    d, keep = capi.make_field_desc(field)
+    for k, v in over.items():
+        setattr(d, k, v)
+    fid = ctypes.c_uint32()
+    return lib.vrn_load_field(None, ctypes.byref(d), ctypes.byref(fid))
+
+
+def test_field_validation(lib):
+    f = synth.field_c1()
+    assert _desc_status(lib, f) == capi.VRN_ERR_INVALID_ARG          # valid field, NULL ctx
+    assert _desc_status(lib, f, n_feat=4) == capi.VRN_ERR_UNSUPPORTED
+    assert _desc_status(lib, f, n_levels=17) == capi.VRN_ERR_UNSUPPORTED
+    assert _desc_status(lib, f, log2_T=30) == capi.VRN_ERR_UNSUPPORTED
+    assert _desc_status(lib, f, mlp_hidden=128) == capi.VRN_ERR_UNSUPPORTED
+    assert _desc_status(lib, f, sh_bands=5) == capi.VRN_ERR_UNSUPPORTED
+    assert _desc_status(lib, f, occ_res=2048) == capi.VRN_ERR_UNSUPPORTED
+    assert _desc_status(lib, f, mlp_in=15) == capi.VRN_ERR_INVALID_ARG
+    assert _desc_status(lib, f, dt=0.0) == capi.VRN_ERR_INVALID_ARG
+    assert _desc_status(lib, f, extent=float("nan")) == capi.VRN_ERR_INVALID_ARG
+    assert _desc_status(lib, f, t_min=1.0) == capi.VRN_ERR_INVALID_ARG
+    assert _desc_status(lib, f, max_samples=0) == capi.VRN_ERR_INVALID_ARG
+    assert _desc_status(lib, f, lod_enable=1, growth=1.0) == capi.VRN_ERR_INVALID_ARG
+    assert _desc_status(lib, f, table_dtype=2) == capi.VRN_ERR_UNSUPPORTED
+    assert "table_dtype" in lib.vrn_last_error().decode()
+
+
+def test_field_file_round_trip_two_readers(tmp_path):
+    """The writer's files are read back identically by the oracle's reader and
+    by the product binding's descriptor marshalling."""
+    from oracle.field_io import load_field
+    f = synth.field_c1()
+    prefix = str(tmp_path / "c1")
+    synth.save_field(prefix, f)
+    g = load_field(prefix)
+    for k in ("level_res", "hash_primes", "tables", "occ_bits", "aabb_min"):
+        assert np.array_equal(np.asarray(g[k]), np.asarray(f[k])), k
+    for k in f["mlp"]:
+        assert np.array_equal(g["mlp"][k], f["mlp"][k])
+    for k in ("n_levels", "log2_T", "occ_res", "max_samples", "sh_bands", "lod_enable"):
+        assert g[k] == f[k]
+    for k in ("extent", "dt", "t_min", "base_res", "growth"):
+        assert np.float32(g[k]) == np.float32(f[k])
+    d1, _ = capi.make_field_desc(f)
+    d2, _ = capi.make_field_desc(g)
+    for name, t in capi.VrnFieldDesc._fields_:
+        if t in (capi.c_u32, capi.c_i32, capi.c_f):
+            assert getattr(d1, name) == getattr(d2, name), name

@@ -1,0 +1,204 @@
+"""GPU stage parity through the C ABI: canonical rays and the occupancy
+march bit-exact, hash encoding and MLPs within tolerance of the FP64
+oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import F32, axis_camera, need_gpu, tiny_field
+from oracle.encoding import encode, level_star, lod_weights
+from oracle.march import dense_masked_march
+from oracle.mlp import color_mlp, density_mlp
+from oracle.rays import canonical_rays, cone_pitch
+from oracle.sh import sh_basis
+from paper_2311_02542_amd import capi, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    need_gpu()
+    r = capi.Renderer(0)
+    yield r
+    r.close()
+
+
+def _rays(R, cams, W, H):
+    torch = R.torch
+    n = len(cams) * W * H
+    o = torch.empty((n, 3), device="cuda")
+    d = torch.empty((n, 3), device="cuda")
+    r = torch.empty(n, device="cuda")
+    capi.vrn_rays(R.ctx, cams, W, H, o, d, r)
+    torch.cuda.synchronize()
+    return o.cpu().numpy(), d.cpu().numpy(), r.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "c4stereo", "axis"])
+def test_rays_bit_exact(R, case):
+    if case == "c1":
+        cams, W, H = synth.cameras_c1(4), 64, 64
+    elif case == "c2":
+        cams, W, H = synth.cameras_c2(2, 96, 72), 96, 72
+    elif case == "c4stereo":
+        cams, W, H = synth.cameras_c4([0, 150], 80, 80)[1], 80, 80
+    else:
+        cams = [axis_camera(np.eye(3), [0.1, 0.2, 0.3]),
+                axis_camera(np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]), [0.5, 0.5, 0.5])]
+        W, H = 8, 8
+    o, d, r = _rays(R, cams, W, H)
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    for c, cam in enumerate(cams):
+        sl = slice(c * W * H, (c + 1) * W * H)
+        oo, dd = canonical_rays(cam, ii.ravel(), jj.ravel())
+        assert np.array_equal(d[sl].view(np.uint32), dd.view(np.uint32)), "direction bits differ"
+        assert np.array_equal(o[sl], oo)
+        rr = cone_pitch(cam, ii.ravel(), jj.ravel())
+        np.testing.assert_allclose(r[sl], rr, rtol=2e-5)
+
+
+def _march(R, field, cams, W, H, max_k):
+    torch = R.torch
+    fid = R.load(field)
+    n = len(cams) * W * H
+    kl = torch.zeros((n, max_k), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    capi.vrn_march(R.ctx, fid, cams, W, H, kl, max_k, cnt)
+    torch.cuda.synchronize()
+    R.unload(fid)
+    return kl.cpu().numpy(), cnt.cpu().numpy()
+
+
+def _check_march(R, field, cams, W, H):
+    max_k = int(field["max_samples"])
+    kl, cnt = _march(R, field, cams, W, H, max_k)
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    total = 0
+    for c, cam in enumerate(cams):
+        o, d = canonical_rays(cam, ii.ravel(), jj.ravel())
+        ks, counts = dense_masked_march(field, o, d)
+        sl = slice(c * W * H, (c + 1) * W * H)
+        assert np.array_equal(cnt[sl], counts), f"cam {c}: {np.sum(cnt[sl] != counts)} count mismatches"
+        for p in np.nonzero(counts)[0]:
+            assert np.array_equal(kl[sl][p, :counts[p]], ks[p, :counts[p]]), (c, p)
+        total += counts.sum()
+    return total
+
+
+def test_march_bit_exact_c1(R):
+    assert _check_march(R, synth.field_c1(), synth.cameras_c1(6), 64, 64) > 1000
+
+
+def test_march_bit_exact_c2_room(R):
+    f = synth.field_c2()
+    assert _check_march(R, f, synth.cameras_c2(2, 72, 56), 72, 56) > 1000
+
+
+@pytest.mark.parametrize("g", [1, 2, 3, 4, 8, 33])
+def test_march_bit_exact_tiny_adversarial(R, g):
+    rng = np.random.default_rng(100 + g)
+    occ = rng.uniform(size=(g, g, g)) < 0.4
+    occ[0, 0, 0] = True
+    amin, ext = (-0.25, 0.5, 1.0), 1.5
+    f = tiny_field(g, occ, amin, ext, cap=10000, seed=g)
+    cell = ext / g
+    cams = []
+    perms = [np.eye(3), np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]), np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]]),
+             -np.eye(3) * np.array([1, -1, 1])]
+    for k in range(8):   # origins on cell faces / edges / corners, inside and outside
+        pos = np.array(amin) + cell * np.array([k % g + (k % 2) * 0.5, (k * 7) % (g + 1), (k * 3) % (g + 1)])
+        if k % 3 == 0:
+            pos = pos - 0.7 * ext
+        cams.append(axis_camera(perms[k % 4], pos, fx=3.0 + k))
+    assert _check_march(R, f, cams, 8, 8) >= 0
+
+
+def test_march_empty_full_and_cap(R):
+    g = 16
+    f0 = tiny_field(g, np.zeros((g, g, g), bool))
+    kl, cnt = _march(R, f0, synth.cameras_c1(2, 16, 16), 16, 16, 8)
+    assert cnt.max() == 0
+    f1 = tiny_field(g, np.ones((g, g, g), bool), cap=7)
+    assert _check_march(R, f1, synth.cameras_c1(2, 16, 16), 16, 16) > 0
+    kl, cnt = _march(R, f1, synth.cameras_c1(1, 16, 16), 16, 16, 7)
+    assert cnt.max() == 7
+
+
+def _sample_points(field, cams, W, H, n_max=20000):
+    """Real sample positions (canonical FP32) with their t and cone pitch."""
+    from oracle.march import canonical_positions
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    xs, ts, rs = [], [], []
+    for cam in cams:
+        o, d = canonical_rays(cam, ii.ravel(), jj.ravel())
+        r = cone_pitch(cam, ii.ravel(), jj.ravel())
+        ks, counts = dense_masked_march(field, o, d)
+        for p in np.nonzero(counts)[0][::3]:
+            k = ks[p, :min(counts[p], 4)]
+            x, t = canonical_positions(o[p:p + 1], d[p:p + 1], k[None, :], field["dt"])
+            xs.append(x[0]); ts.append(t[0]); rs.append(np.full(k.size, r[p]))
+    x = np.concatenate(xs)[:n_max].astype(F32)
+    return x, np.concatenate(ts)[:n_max].astype(F32), np.concatenate(rs)[:n_max].astype(F32)
+
+
+@pytest.mark.parametrize("case", ["c1", "c2_lod", "c4_levels_f16", "c4_levels_f32"])
+def test_encode_parity(R, case):
+    torch = R.torch
+    if case == "c1":
+        f = synth.field_c1()
+        x, t, r = _sample_points(f, synth.cameras_c1(4), 64, 64)
+    elif case == "c2_lod":
+        f = synth.field_c2()
+        x, t, r = _sample_points(f, synth.cameras_c2(2, 64, 64), 64, 64)
+    else:
+        # config-4 level resolutions (up to N = 19912 over a 16 m cube) on a smaller table
+        rng = np.random.default_rng(7)
+        f = tiny_field(8, np.ones((8, 8, 8), bool), (0, 0, 0), 16.0, L=16, log2_T=16, lod=True,
+                       bands=4, table_dtype=np.float16 if case.endswith("f16") else np.float32)
+        f["level_res"] = synth.level_resolutions(16, 128.0, 1.4)
+        f["base_res"], f["growth"] = 128.0, float(F32(1.4))
+        x = rng.uniform(0, 16, (20000, 3)).astype(F32)
+        t = rng.uniform(0.05, 12, 20000).astype(F32)
+        r = np.full(20000, F32(1.0 / 859.24))
+    fid = R.load(f)
+    n = x.shape[0]
+    L = int(f["n_levels"])
+    dx, dt_, dr = (torch.from_numpy(a).cuda() for a in (x, t, r))
+    feat = torch.full((n, 2 * L), float("nan"), device="cuda")
+    capi.vrn_encode(R.ctx, fid, dx, dt_, dr, n, feat)
+    torch.cuda.synchronize()
+    R.unload(fid)
+    g = feat.cpu().numpy()
+    w = lod_weights(level_star(t.astype(np.float64), r.astype(np.float64), f), L) if f["lod_enable"] else None
+    ref = encode(f, x, w)
+    err = np.abs(g - ref)
+    assert np.isfinite(g).all()
+    assert err.max() <= 1e-6, f"max abs feature error {err.max():.3g}"
+
+
+@pytest.mark.parametrize("compute,tol_rgb,tol_sig", [("f32", 1e-6, 2e-6), ("f16", 5e-3, 5e-2),
+                                                     ("bf16", 3e-2, 3e-1)])
+@pytest.mark.parametrize("case", ["c1", "c2"])
+def test_mlp_parity(R, case, compute, tol_rgb, tol_sig):
+    torch = R.torch
+    f = synth.field_c1() if case == "c1" else synth.field_c2()
+    L = int(f["n_levels"])
+    rng = np.random.default_rng(11)
+    n = 4099  # ragged tail of a 16-sample tile
+    feats = rng.uniform(-0.1, 0.1, (n, 2 * L)).astype(F32)
+    d = rng.standard_normal((n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(F32)
+    fid = R.load(f)
+    sig = torch.empty(n, device="cuda")
+    rgb = torch.empty((n, 3), device="cuda")
+    capi.vrn_mlp(R.ctx, fid, torch.from_numpy(feats).cuda(), torch.from_numpy(d).cuda(), n, compute, sig, rgb)
+    torch.cuda.synchronize()
+    R.unload(fid)
+    s_ref, geo = density_mlp(feats.astype(np.float64), f["mlp"])
+    c_ref = color_mlp(geo, sh_basis(d.astype(np.float64), int(f["sh_bands"])), f["mlp"])
+    s_err = np.abs(sig.cpu().numpy() / s_ref - 1)
+    c_err = np.abs(rgb.cpu().numpy() - c_ref)
+    assert s_err.max() <= tol_sig, f"sigma rel err {s_err.max():.3g}"
+    assert c_err.max() <= tol_rgb, f"rgb abs err {c_err.max():.3g}"

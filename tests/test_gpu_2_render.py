@@ -1,0 +1,150 @@
+"""Whole-image GPU parity through vrn_render: FP32 path within 1e-5 PQ of
+the FP64 oracle with bit-exact sample counts (ties excepted), at small
+sizes on whole images and at full workload sizes on sampled pixels; edge
+cases (empty scenes, cameras outside the volume, ragged images, row shares,
+several cameras), linear-HDR output and determinism."""
+import numpy as np
+import pytest
+
+from gpu_common import F32, axis_camera, compare_render, need_gpu, tiny_field
+from oracle.pq import pq_to_linear
+from oracle.render import all_pixels, render_fp64
+from paper_2311_02542_amd import capi, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def R():
+    need_gpu()
+    r = capi.Renderer(0)
+    yield r
+    r.close()
+
+
+def gpu_render(R, field, cams, W, H, compute="f32", linear=False, fid=None):
+    own = fid is None
+    if own:
+        fid = R.load(field)
+    rgba, ns = R.render(fid, cams, W, H, compute, linear)
+    R.torch.cuda.synchronize()
+    if own:
+        R.unload(fid)
+    return rgba.cpu().numpy(), ns.cpu().numpy()
+
+
+def test_c1_whole_images(R):
+    f = synth.field_c1()
+    cams = synth.cameras_c1(6)
+    rgba, ns = gpu_render(R, f, cams, 64, 64)
+    ref = render_fp64(f, cams, 64, 64)
+    mx, mean, ties = compare_render(rgba, ns, ref, TOL)
+    print(f"c1 max {mx:.3g} mean {mean:.3g} ties {ties}")
+    assert mx <= TOL
+
+
+def test_c2_whole_image_ragged(R):
+    f = synth.field_c2()
+    cams = synth.cameras_c2(2, 100, 77)     # 13 x 10 tiles with ragged edges
+    rgba, ns = gpu_render(R, f, cams, 100, 77)
+    ref = render_fp64(f, cams, 100, 77)
+    mx, mean, ties = compare_render(rgba, ns, ref, TOL)
+    print(f"c2 small max {mx:.3g} mean {mean:.3g} ties {ties}")
+    assert mx <= TOL
+    assert ref["n"].sum() > 5000
+
+
+def test_c2_full_size_sampled(R):
+    f = synth.field_c2()
+    cams = synth.cameras_c2(1)
+    rgba, ns = gpu_render(R, f, cams, 1024, 1024)
+    rng = np.random.default_rng(3)
+    px = np.stack([np.zeros(1500, int), rng.integers(0, 1024, 1500), rng.integers(0, 1024, 1500)], 1)
+    ref = render_fp64(f, cams, 1024, 1024, pixels=px)
+    sel = px[:, 1] * 1024 + px[:, 2]
+    mx, mean, ties = compare_render(rgba.reshape(-1, 4)[sel], ns.reshape(-1)[sel], ref, TOL)
+    print(f"c2 1024^2 sampled max {mx:.3g} mean {mean:.3g} ties {ties}")
+    assert mx <= TOL
+
+
+def test_c4_stereo_full_size_sampled_fp32(R):
+    f = synth.field_c4(table_dtype=np.float32)
+    cams = synth.cameras_c4([0])[0]
+    rgba, ns = gpu_render(R, f, cams, 2048, 2048)
+    rng = np.random.default_rng(4)
+    m = 300
+    px = np.stack([rng.integers(0, 2, m), rng.integers(0, 2048, m), rng.integers(0, 2048, m)], 1)
+    ref = render_fp64(f, cams, 2048, 2048, pixels=px)
+    sel = (px[:, 0] * 2048 + px[:, 1]) * 2048 + px[:, 2]
+    mx, mean, ties = compare_render(rgba.reshape(-1, 4)[sel], ns.reshape(-1)[sel], ref, TOL)
+    print(f"c4 stereo sampled max {mx:.3g} mean {mean:.3g} ties {ties}")
+    assert mx <= TOL
+    assert ref["n"].sum() > 0
+
+
+def test_empty_grid_and_camera_outside(R):
+    g = 16
+    f = tiny_field(g, np.zeros((g, g, g), bool))
+    rgba, ns = gpu_render(R, f, synth.cameras_c1(2, 32, 32), 32, 32)
+    assert np.all(rgba == 0) and np.all(ns == 0)
+    f = tiny_field(g, np.ones((g, g, g), bool), cap=32)
+    # outside the cube, looking away from it (+z from above the top face)
+    cam = axis_camera(np.eye(3), [0.5, 0.5, 1.5], W=16, H=16, fx=20.0, cx=8.0, cy=8.0)
+    rgba, ns = gpu_render(R, f, [cam], 16, 16)
+    assert np.all(rgba == 0) and np.all(ns == 0)
+    # outside, looking at it: same as the oracle
+    cam = axis_camera(np.eye(3), [0.5, 0.5, -0.5], W=16, H=16, fx=20.0, cx=8.0, cy=8.0)
+    rgba, ns = gpu_render(R, f, [cam], 16, 16)
+    ref = render_fp64(f, [cam], 16, 16)
+    mx, _, _ = compare_render(rgba, ns, ref, TOL)
+    assert mx <= TOL and ns.min() > 0
+
+
+def test_row_shares_and_several_cameras(R):
+    torch = R.torch
+    f = synth.field_c1()
+    base = synth.cameras_c1(3, 48, 40)
+    fid = R.load(f)
+    full, full_n = gpu_render(R, f, base, 48, 40, fid=fid)
+    shares = [dict(base[0], row_begin=0, row_end=13), dict(base[1], row_begin=13, row_end=40),
+              dict(base[2], row_begin=5, row_end=6)]
+    rgba = torch.full((3, 40, 48, 4), -7.0, device="cuda")
+    ns = torch.full((3, 40, 48), -7, dtype=torch.int32, device="cuda")
+    R.render(fid, shares, 48, 40, out=(rgba, ns))
+    torch.cuda.synchronize()
+    R.unload(fid)
+    a, n = rgba.cpu().numpy(), ns.cpu().numpy()
+    for c, (rb, re) in enumerate([(0, 13), (13, 40), (5, 6)]):
+        assert np.array_equal(a[c, rb:re], full[c, rb:re])
+        assert np.array_equal(n[c, rb:re], full_n[c, rb:re])
+        assert np.all(a[c, :rb] == -7) and np.all(a[c, re:] == -7)
+
+
+def test_linear_hdr_output(R):
+    f = synth.field_c1()
+    cams = synth.cameras_c1(2)
+    pq, _ = gpu_render(R, f, cams, 64, 64)
+    lin, _ = gpu_render(R, f, cams, 64, 64, linear=True)
+    np.testing.assert_allclose(lin[..., :3], pq_to_linear(pq[..., :3].astype(np.float64)), rtol=2e-4, atol=1e-7)
+    assert np.array_equal(lin[..., 3], pq[..., 3])
+
+
+def test_deterministic_and_workspace_reuse(R):
+    torch = R.torch
+    f = synth.field_c2()
+    cams = synth.cameras_c2(1, 256, 256)
+    fid = R.load(f)
+    a1, n1 = gpu_render(R, f, cams, 256, 256, fid=fid)
+    a2, n2 = gpu_render(R, f, cams, 256, 256, fid=fid)
+    ws = torch.zeros(capi.vrn_workspace_bytes(R.ctx), dtype=torch.uint8, device="cuda")
+    capi.vrn_workspace_init(R.ctx, ws)
+    rgba = torch.zeros((1, 256, 256, 4), device="cuda")
+    ns = torch.zeros((1, 256, 256), dtype=torch.int32, device="cuda")
+    capi.vrn_render(R.ctx, fid, cams, 256, 256, rgba, ns, workspace=ws)
+    torch.cuda.synchronize()
+    st = capi.vrn_read_stats(R.ctx, ws)
+    R.unload(fid)
+    assert np.array_equal(a1, a2) and np.array_equal(n1, n2)
+    assert np.array_equal(a1, rgba.cpu().numpy()) and np.array_equal(n1, ns.cpu().numpy())
+    assert st["rays"] == 256 * 256 and st["samples"] == int(n1.sum())
