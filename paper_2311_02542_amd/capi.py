@@ -181,7 +181,10 @@ def make_cameras(cams, H):
 
 
 def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    """Device pointer of a tensor (or a raw integer address)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(int(t) if isinstance(t, int) else t.data_ptr())
 
 
 def _stream(stream):

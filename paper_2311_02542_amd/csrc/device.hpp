@@ -232,14 +232,33 @@ __device__ __forceinline__ void two_diff(float a, float b, float& hi, float& lo)
 
 // Base lattice corner and fraction of p = u * S computed as a double-float
 // (u = uh + ul exact, S = s_hi + s_lo): the fraction is accurate to one
-// rounding even at 2e4-cell levels.
+// rounding even at 2e4-cell levels.  When ph alone rounds onto the integer
+// above (below) the true p, the low part makes the fraction negative (>= 1)
+// and the corner is moved to the cell that really contains p; otherwise the
+// interpolation would extrapolate from the neighbouring cell.
 __device__ __forceinline__ uint32_t base_corner(float uh, float ul, float shi, float slo, uint32_t N,
                                                 float& fr) {
   const float ph = uh * shi;
   const float pe = fmaf(uh, shi, -ph);
   const float pl = pe + (uh * slo + ul * shi);
-  const float fi = fminf(fmaxf(floorf(ph), 0.0f), (float)(N - 1));
-  fr = (ph - fi) + pl;
+  float fi = floorf(ph);
+  float f = (ph - fi) + pl;
+  if (f < 0.0f) {
+    fi -= 1.0f;
+    f += 1.0f;
+  } else if (f >= 1.0f) {
+    fi += 1.0f;
+    f -= 1.0f;
+  }
+  const float top = (float)(N - 1);
+  if (fi > top) {
+    f += fi - top;
+    fi = top;
+  } else if (fi < 0.0f) {
+    f += fi;
+    fi = 0.0f;
+  }
+  fr = f;
   return (uint32_t)fi;
 }
 
@@ -383,13 +402,19 @@ __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ v4f bias4(const float* sb, int base, int g) {
-  v4f b;
-  b[0] = sb[base + 4 * g + 0];
-  b[1] = sb[base + 4 * g + 1];
-  b[2] = sb[base + 4 * g + 2];
-  b[3] = sb[base + 4 * g + 3];
-  return b;
+__device__ __forceinline__ v4f zero4() {
+  v4f z;
+  z[0] = z[1] = z[2] = z[3] = 0.0f;
+  return z;
+}
+
+// Biases are added after the MFMA accumulation: the density bias is large
+// (several units) next to the products, and adding it last rounds it once.
+__device__ __forceinline__ v4f add_bias4(v4f v, const float* sb, int base, int g) {
+  v4f r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = v[i] + sb[base + 4 * g + i];
+  return r;
 }
 
 __device__ __forceinline__ v4f relu4(v4f v) {
@@ -406,7 +431,7 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
   const int g = lane >> 4;
   v4f h[4];
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) h[ot] = bias4(sb, kB1 + 16 * ot, g);
+  for (int ot = 0; ot < 4; ++ot) h[ot] = zero4();
   for (uint32_t s4 = 0; s4 < d1_groups; ++s4) {
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
@@ -418,8 +443,8 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     }
   }
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) h[ot] = relu4(h[ot]);
-  v4f o = bias4(sb, kB2, g);
+  for (int ot = 0; ot < 4; ++ot) h[ot] = relu4(add_bias4(h[ot], sb, kB1 + 16 * ot, g));
+  v4f o = zero4();
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     const float4 w = sw[kW32_D2 / 4 + it * 64 + lane];
@@ -428,10 +453,11 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     o = mfma_f32(w.z, h[it][2], o);
     o = mfma_f32(w.w, h[it][3], o);
   }
+  o = add_bias4(o, sb, kB2, g);
   v4f c1[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) {
-    c1[ot] = bias4(sb, kB3 + 16 * ot, g);
+    c1[ot] = zero4();
     const float4 w0 = sw[kW32_C1 / 4 + (ot * 2 + 0) * 64 + lane];
     c1[ot] = mfma_f32(w0.x, o[0], c1[ot]);
     c1[ot] = mfma_f32(w0.y, o[1], c1[ot]);
@@ -444,11 +470,11 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     c1[ot] = mfma_f32(w1.w, shs[3], c1[ot]);
   }
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) c1[ot] = relu4(c1[ot]);
+  for (int ot = 0; ot < 4; ++ot) c1[ot] = relu4(add_bias4(c1[ot], sb, kB3 + 16 * ot, g));
   v4f c2[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) {
-    c2[ot] = bias4(sb, kB4 + 16 * ot, g);
+    c2[ot] = zero4();
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const float4 w = sw[kW32_C2 / 4 + (ot * 4 + it) * 64 + lane];
@@ -459,8 +485,8 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     }
   }
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) c2[ot] = relu4(c2[ot]);
-  v4f c3 = bias4(sb, kB5, g);
+  for (int ot = 0; ot < 4; ++ot) c2[ot] = relu4(add_bias4(c2[ot], sb, kB4 + 16 * ot, g));
+  v4f c3 = zero4();
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     const float4 w = sw[kW32_C3 / 4 + it * 64 + lane];
@@ -469,6 +495,7 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     c3 = mfma_f32(w.z, c2[it][2], c3);
     c3 = mfma_f32(w.w, c2[it][3], c3);
   }
+  c3 = add_bias4(c3, sb, kB5, g);
   o0 = o[0];
   lg[0] = c3[0];
   lg[1] = c3[1];
@@ -521,20 +548,21 @@ __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const 
   const vec xin = H::pack(feat);
   v4f h[4];
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) h[ot] = H::mfma(wfrag(kW16_D1, ot), xin, bias4(sb, kB1 + 16 * ot, g));
+  for (int ot = 0; ot < 4; ++ot) h[ot] = add_bias4(H::mfma(wfrag(kW16_D1, ot), xin, zero4()), sb, kB1 + 16 * ot, g);
   float hv[16];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
     for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(h[ot][r], 0.0f);
-  v4f o = bias4(sb, kB2, g);
+  v4f o = zero4();
   o = H::mfma(wfrag(kW16_D2, 0), H::pack(hv), o);
   o = H::mfma(wfrag(kW16_D2, 1), H::pack(hv + 8), o);
+  o = add_bias4(o, sb, kB2, g);
   float cin[8] = {o[0], o[1], o[2], o[3], shs[0], shs[1], shs[2], shs[3]};
   const vec cv = H::pack(cin);
   v4f c1[4];
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) c1[ot] = H::mfma(wfrag(kW16_C1, ot), cv, bias4(sb, kB3 + 16 * ot, g));
+  for (int ot = 0; ot < 4; ++ot) c1[ot] = add_bias4(H::mfma(wfrag(kW16_C1, ot), cv, zero4()), sb, kB3 + 16 * ot, g);
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
@@ -543,17 +571,19 @@ __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const 
   v4f c2[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) {
-    c2[ot] = bias4(sb, kB4 + 16 * ot, g);
+    c2[ot] = zero4();
     c2[ot] = H::mfma(wfrag(kW16_C2, ot * 2 + 0), a0, c2[ot]);
     c2[ot] = H::mfma(wfrag(kW16_C2, ot * 2 + 1), a1, c2[ot]);
+    c2[ot] = add_bias4(c2[ot], sb, kB4 + 16 * ot, g);
   }
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
     for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(c2[ot][r], 0.0f);
-  v4f c3 = bias4(sb, kB5, g);
+  v4f c3 = zero4();
   c3 = H::mfma(wfrag(kW16_C3, 0), H::pack(hv), c3);
   c3 = H::mfma(wfrag(kW16_C3, 1), H::pack(hv + 8), c3);
+  c3 = add_bias4(c3, sb, kB5, g);
   o0 = o[0];
   lg[0] = c3[0];
   lg[1] = c3[1];
