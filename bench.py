@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-error", action="store_true", help="skip the PQ error check")
     ap.add_argument("--cpu-crop", type=int, default=256, help="oracle crop side per eye")
     ap.add_argument("--error-pixels", type=int, default=4096)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, run one plain 1 GiB device copy (to scale profiler byte counters)")
     return ap.parse_args()
 
 
@@ -188,6 +190,14 @@ def main():
                  "frac": hr["mfma_TFLOPs"] / MFMA_PEAK_TFLOPS[head]},
         "context": "paper: dual 2Kx2K at 36 Hz on a 20x A40 demo machine (~302 Mrays/s aggregate), not comparable",
     }
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(field32, frames[0], W, H, args.cpu_crop)
     R.close()

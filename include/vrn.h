@@ -110,6 +110,8 @@ typedef struct {
   uint64_t samples;           /* evaluated samples composited */
   uint64_t level_fetches;     /* hash levels gathered (8 corners each) */
   uint64_t march_steps;       /* canonical lattice tests + block skips */
+  uint64_t rounds;            /* wave rounds (march, then encode + MLP of the samples found) */
+  uint64_t tiles;             /* 16-sample MLP tiles evaluated */
 } vrn_stats;
 
 #define VRN_MAX_CAMS 16

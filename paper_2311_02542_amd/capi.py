@@ -55,7 +55,7 @@ class VrnRenderOpts(ctypes.Structure):
 
 class VrnStats(ctypes.Structure):
     _fields_ = [("rays", c_u64), ("samples", c_u64), ("level_fetches", c_u64),
-                ("march_steps", c_u64)]
+                ("march_steps", c_u64), ("rounds", c_u64), ("tiles", c_u64)]
 
 
 class VrnError(RuntimeError):
@@ -284,8 +284,7 @@ def vrn_read_stats(ctx, workspace=None, stream=None) -> dict:
     lib = load_library()
     st = VrnStats()
     _check(lib.vrn_read_stats(ctx, _ptr(workspace), ctypes.byref(st), _stream(stream)), lib)
-    return {"rays": st.rays, "samples": st.samples, "level_fetches": st.level_fetches,
-            "march_steps": st.march_steps}
+    return {name: int(getattr(st, name)) for name, _ in VrnStats._fields_}
 
 
 def vrn_rays(ctx, cams, W, H, o, d, r, scale=1.0, stream=None):

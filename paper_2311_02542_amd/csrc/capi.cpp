@@ -252,7 +252,7 @@ vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t 
   a.nsamples = d_nsamples;
   a.ws = static_cast<uint8_t*>(ws);
   a.linear_hdr = opts ? opts->output_linear_hdr : 0;
-  a.budget = (opts && opts->march_budget) ? opts->march_budget : 64u;
+  a.budget = (opts && opts->march_budget) ? opts->march_budget : 256u;
   const int compute = opts ? (int)opts->compute : 0;
   const uint64_t rays = (uint64_t)n_cams * W * H;
   const uint64_t want = (rays + kBlock - 1) / kBlock;
@@ -328,10 +328,14 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   for (uint64_t i = 0; i < nw; ++i)
     if (!finite(d->weights[i])) return fail(VRN_ERR_INVALID_ARG, "MLP weights contain non-finite values");
 
-  // coarse occupancy: OR over blocks of 2^bshift cells per axis
-  const uint32_t bshift = G >= 128 ? 3u : (G >= 16 ? 2u : 0u);
-  const uint32_t Gc = (G + (1u << bshift) - 1) >> bshift;
+  // occupancy: 4x4x4 bricks (one 64-bit word each) and a coarse grid of
+  // <= 32^3 blocks (2^cshift cells, a multiple of the brick) for LDS
+  const uint32_t Gb = (G + 3) / 4;
+  uint32_t cshift = 2;
+  while (((G + (1u << cshift) - 1) >> cshift) > 32u) ++cshift;
+  const uint32_t Gc = (G + (1u << cshift) - 1) >> cshift;
   const uint64_t n_fine = (uint64_t)G * G * G, n_words = (n_fine + 31) / 32;
+  std::vector<unsigned long long> bricks((size_t)Gb * Gb * Gb, 0ull);
   std::vector<uint32_t> coarse(((uint64_t)Gc * Gc * Gc + 31) / 32, 0u);
   for (uint64_t w = 0; w < n_words; ++w) {
     uint32_t word = d->occ_bits[w];
@@ -341,7 +345,9 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
       const uint64_t i = w * 32 + (uint64_t)b;
       if (i >= n_fine) break;
       const uint32_t x = (uint32_t)(i % G), y = (uint32_t)((i / G) % G), z = (uint32_t)(i / ((uint64_t)G * G));
-      const uint64_t ci = (x >> bshift) + (uint64_t)Gc * ((y >> bshift) + (uint64_t)Gc * (z >> bshift));
+      const uint64_t bi = (x >> 2) + (uint64_t)Gb * ((y >> 2) + (uint64_t)Gb * (z >> 2));
+      bricks[bi] |= 1ull << ((x & 3) + 4 * (y & 3) + 16 * (z & 3));
+      const uint64_t ci = (x >> cshift) + (uint64_t)Gc * ((y >> cshift) + (uint64_t)Gc * (z >> cshift));
       coarse[ci >> 5] |= 1u << (ci & 31);
     }
   }
@@ -363,7 +369,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
     P.pad = 0;
   }
   const uint64_t tab_bytes = n_tab * (d->table_dtype == VRN_F16 ? 2 : 4);
-  const uint64_t need = tab_bytes + n_words * 4 + coarse.size() * 4 + (w32.size() + bias.size()) * 4 +
+  const uint64_t need = tab_bytes + bricks.size() * 8 + coarse.size() * 4 + (w32.size() + bias.size()) * 4 +
                         (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev);
   if (ctx->budget && ctx->used + need > ctx->budget)
     return fail(VRN_ERR_BUDGET, "loading the field would exceed the HBM budget");
@@ -374,11 +380,12 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   FieldDev& F = f->dev;
   uint8_t* tab = nullptr;
   LevelDev* dlv = nullptr;
-  uint32_t *docc = nullptr, *dco = nullptr;
+  unsigned long long* dbr = nullptr;
+  uint32_t* dco = nullptr;
   float *dw32 = nullptr, *dbias = nullptr;
   uint16_t *dw16 = nullptr, *dwbf = nullptr;
   if ((e = upload(f, static_cast<const uint8_t*>(d->tables), tab_bytes, &tab)) ||
-      (e = upload(f, lv.data(), lv.size(), &dlv)) || (e = upload(f, d->occ_bits, n_words, &docc)) ||
+      (e = upload(f, lv.data(), lv.size(), &dlv)) || (e = upload(f, bricks.data(), bricks.size(), &dbr)) ||
       (e = upload(f, coarse.data(), coarse.size(), &dco)) || (e = upload(f, w32.data(), w32.size(), &dw32)) ||
       (e = upload(f, w16.data(), w16.size(), &dw16)) || (e = upload(f, wbf.data(), wbf.size(), &dwbf)) ||
       (e = upload(f, bias.data(), bias.size(), &dbias))) {
@@ -388,8 +395,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   }
   F.tables = tab;
   F.levels = dlv;
-  F.occ = docc;
-  F.occ_coarse = dco;
+  F.bricks = dbr;
+  F.coarse = dco;
   F.w32 = dw32;
   F.w16 = dw16;
   F.wbf = dwbf;
@@ -399,8 +406,9 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.Tmask = (uint32_t)(T - 1);
   F.table_f16 = d->table_dtype == VRN_F16;
   F.G = G;
+  F.Gb = Gb;
   F.Gc = Gc;
-  F.bshift = bshift;
+  F.cshift = cshift;
   F.nsh = nsh;
   for (int a = 0; a < 3; ++a) F.amin[a] = d->aabb_min[a];
   F.cs = (float)((double)G / (double)d->extent);
@@ -414,6 +422,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.lod_bias = d->lod_bias;
   F.lod_radius_scale = d->lod_enable ? d->lod_radius_scale : 1.0f;
   F.d1_ksteps = L > 8 ? 8u : 4u;
+  F.dense_mask = 0;
+  for (uint32_t l = 0; l < L; ++l) F.dense_mask |= lv[l].dense << l;
   F.c1_ksteps = 8u;
   const vrn_field_id id = ctx->next_id++;
   ctx->fields[id] = f;
@@ -516,7 +526,7 @@ vrn_status vrn_read_stats(vrn_ctx* ctx, const void* ws, vrn_stats* out, void* st
   hipSetDevice(ctx->device);
   const uint8_t* w = static_cast<const uint8_t*>(ws ? ws : ctx->ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  uint64_t v[4];
+  uint64_t v[6];
   hipError_t e = hipMemcpyAsync(v, w + kWsStats, sizeof(v), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "stats read");
@@ -524,6 +534,8 @@ vrn_status vrn_read_stats(vrn_ctx* ctx, const void* ws, vrn_stats* out, void* st
   out->samples = v[1];
   out->level_fetches = v[2];
   out->march_steps = v[3];
+  out->rounds = v[4];
+  out->tiles = v[5];
   return VRN_OK;
 }
 

@@ -51,6 +51,8 @@ struct Ray {
   float lr;      // ln(r) + ln(2 s / extent): log of the LOD footprint per unit t
   float delta;   // block-skip margin in cell units (bounds FP32 rounding of q)
   int k, k_hi;   // lattice cursor and last lattice index worth testing
+  int brick;     // index of the 4x4x4 brick whose bits are cached below (-1: none)
+  uint32_t blo, bhi;
 };
 
 // Canonical FP32 direction: a = ((i + .5) - cx) / fx, b = ((j + .5) - cy) / fy,
@@ -125,6 +127,8 @@ __device__ __forceinline__ void setup_ray(const FieldDev& F, const vrn_camera& c
   r.dy = d[1];
   r.dz = d[2];
   r.lr = F.lod ? logf(cone_pitch(c, w, n, F.lod_radius_scale)) + F.lod_c : 0.0f;
+  r.brick = -1;
+  r.blo = r.bhi = 0u;
   lattice_range(F, r);
 }
 
@@ -151,68 +155,89 @@ __device__ __forceinline__ bool bit_set(const uint32_t* bits, uint32_t idx) {
   return (bits[idx >> 5] >> (idx & 31u)) & 1u;
 }
 
+// Jump past the lattice samples that stay inside the empty box of `size`
+// cells with corner o (cell units), shrunk by delta.  The jump is taken only
+// when the current sample (q) and the landing sample both lie in the shrunk
+// box: by convexity every lattice sample in between lies in it too, and
+// delta >= twice the FP32 error of q, so no sample whose canonical cell is
+// occupied is ever passed.  Returns true if r.k moved.
+__device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float q[3], int ox, int oy, int oz,
+                                         float size) {
+  const float lo[3] = {ox * size + r.delta, oy * size + r.delta, oz * size + r.delta};
+  const float hi[3] = {(ox + 1) * size - r.delta, (oy + 1) * size - r.delta, (oz + 1) * size - r.delta};
+  if (!(q[0] >= lo[0] && q[0] <= hi[0] && q[1] >= lo[1] && q[1] <= hi[1] && q[2] >= lo[2] && q[2] <= hi[2]))
+    return false;
+  const float o[3] = {r.ox, r.oy, r.oz};
+  const float d[3] = {r.dx, r.dy, r.dz};
+  float te = 3.0e38f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float bq = signbit(d[a]) ? lo[a] : hi[a];
+    te = fminf(te, (bq / F.cs + F.amin[a] - o[a]) / d[a]);
+  }
+  const float kbf = fminf(floorf(te / F.dt - 0.5f), (float)r.k_hi);
+  if (!(kbf >= (float)r.k + 2.0f)) return false;
+  int kb = (int)kbf;
+#pragma unroll
+  for (int tries = 0; tries < 2; ++tries, --kb) {
+    float t2, x2[3], q2[3];
+    lattice_q(F, r, kb, t2, x2, q2);
+    if (q2[0] >= lo[0] && q2[0] <= hi[0] && q2[1] >= lo[1] && q2[1] <= hi[1] && q2[2] >= lo[2] &&
+        q2[2] <= hi[2]) {
+      r.k = kb + 1;
+      return true;
+    }
+  }
+  return false;
+}
+
 // Advance to the next evaluated sample within `budget` lattice tests.
-// Returns 1 (sample found; t, x are its canonical values), 0 (budget used
-// up) or 2 (ray exhausted).  Empty space is skipped a coarse block at a time
-// when the current sample and the landing sample both lie in the same empty
-// block shrunk by delta: by convexity every lattice sample in between then
-// lies in that block too (delta >= twice the FP32 error of q), so the skip
-// never passes a sample whose canonical cell is occupied.
-__device__ __forceinline__ int march_next(const FieldDev& F, Ray& r, uint32_t budget, uint32_t& steps,
-                                          float& st, float sx[3]) {
+// Returns 1 (sample found; st, sx are its canonical t and x), 0 (budget used
+// up) or 2 (ray exhausted).  Occupancy is tested hierarchically: the coarse
+// grid (blocks of 2^cshift cells, in LDS), then the 4x4x4 brick (one 64-bit
+// load, kept in registers while the ray stays in the brick), then the cell
+// bit.  Empty coarse blocks and empty bricks are skipped with skip_box.
+__device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coarse, Ray& r, uint32_t budget,
+                                          uint32_t& steps, float& st, float sx[3]) {
   const int G = (int)F.G;
-  const float B = (float)(1u << F.bshift);
+  const float cb = (float)(1u << F.cshift);
   for (uint32_t it = 0; it < budget; ++it) {
     if (r.k > r.k_hi) return 2;
     ++steps;
     float t, x[3], q[3];
     lattice_q(F, r, r.k, t, x, q);
     const int cx = cell_of(q[0], G), cy = cell_of(q[1], G), cz = cell_of(q[2], G);
-    bool skipped = false;
+    bool moved = false;
     if ((unsigned)cx < (unsigned)G && (unsigned)cy < (unsigned)G && (unsigned)cz < (unsigned)G) {
-      const uint32_t idx = (uint32_t)cx + (uint32_t)G * ((uint32_t)cy + (uint32_t)G * (uint32_t)cz);
-      if (bit_set(F.occ, idx)) {
-        st = t;
-        sx[0] = x[0];
-        sx[1] = x[1];
-        sx[2] = x[2];
-        r.k++;
-        return 1;
-      }
-      const int bx = cx >> F.bshift, by = cy >> F.bshift, bz = cz >> F.bshift;
-      const uint32_t bidx = (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz);
-      if (!bit_set(F.occ_coarse, bidx)) {
-        const float lo[3] = {bx * B + r.delta, by * B + r.delta, bz * B + r.delta};
-        const float hi[3] = {(bx + 1) * B - r.delta, (by + 1) * B - r.delta, (bz + 1) * B - r.delta};
-        const bool in0 = q[0] >= lo[0] && q[0] <= hi[0] && q[1] >= lo[1] && q[1] <= hi[1] &&
-                         q[2] >= lo[2] && q[2] <= hi[2];
-        if (in0) {
-          const float o[3] = {r.ox, r.oy, r.oz};
-          const float d[3] = {r.dx, r.dy, r.dz};
-          float te = 3.0e38f;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const float bq = signbit(d[a]) ? lo[a] : hi[a];
-            te = fminf(te, (bq / F.cs + F.amin[a] - o[a]) / d[a]);
-          }
-          const float kbf = fminf(floorf(te / F.dt - 0.5f), (float)r.k_hi);
-          if (kbf >= (float)r.k + 2.0f) {
-            int kb = (int)kbf;
-#pragma unroll
-            for (int tries = 0; tries < 2 && !skipped; ++tries, --kb) {
-              float t2, x2[3], q2[3];
-              lattice_q(F, r, kb, t2, x2, q2);
-              if (q2[0] >= lo[0] && q2[0] <= hi[0] && q2[1] >= lo[1] && q2[1] <= hi[1] &&
-                  q2[2] >= lo[2] && q2[2] <= hi[2]) {
-                r.k = kb + 1;
-                skipped = true;
-              }
-            }
+      const int bx = cx >> F.cshift, by = cy >> F.cshift, bz = cz >> F.cshift;
+      if (!bit_set(coarse, (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz))) {
+        moved = skip_box(F, r, q, bx, by, bz, cb);
+      } else {
+        const int kx = cx >> 2, ky = cy >> 2, kz = cz >> 2;
+        const int brick = kx + (int)F.Gb * (ky + (int)F.Gb * kz);
+        if (brick != r.brick) {
+          const unsigned long long b = F.bricks[brick];
+          r.brick = brick;
+          r.blo = (uint32_t)b;
+          r.bhi = (uint32_t)(b >> 32);
+        }
+        if ((r.blo | r.bhi) == 0u) {
+          moved = skip_box(F, r, q, kx, ky, kz, 4.0f);
+        } else {
+          const uint32_t bit = (uint32_t)((cx & 3) + 4 * (cy & 3) + 16 * (cz & 3));
+          const uint32_t word = bit < 32u ? r.blo : r.bhi;
+          if ((word >> (bit & 31u)) & 1u) {
+            st = t;
+            sx[0] = x[0];
+            sx[1] = x[1];
+            sx[2] = x[2];
+            r.k++;
+            return 1;
           }
         }
       }
     }
-    if (!skipped) r.k++;
+    if (!moved) r.k++;
   }
   return 0;
 }
@@ -233,93 +258,88 @@ __device__ __forceinline__ void two_diff(float a, float b, float& hi, float& lo)
 // Base lattice corner and fraction of p = u * S computed as a double-float
 // (u = uh + ul exact, S = s_hi + s_lo): the fraction is accurate to one
 // rounding even at 2e4-cell levels.  When ph alone rounds onto the integer
-// above (below) the true p, the low part makes the fraction negative (>= 1)
-// and the corner is moved to the cell that really contains p; otherwise the
-// interpolation would extrapolate from the neighbouring cell.
-__device__ __forceinline__ uint32_t base_corner(float uh, float ul, float shi, float slo, uint32_t N,
-                                                float& fr) {
+// above (below) the true p, the low part makes the fraction negative (>= 1);
+// floor(f) moves the corner to the cell that really contains p, otherwise
+// the interpolation would extrapolate from the neighbouring cell.  The
+// corner is then clamped to [0, N-1] with the fraction carrying the rest
+// (so p = N gives the last cell with fraction 1).
+__device__ __forceinline__ uint32_t base_corner(float uh, float ul, float shi, float slo, float top, float& fr) {
   const float ph = uh * shi;
   const float pe = fmaf(uh, shi, -ph);
   const float pl = pe + (uh * slo + ul * shi);
-  float fi = floorf(ph);
+  const float fi = floorf(ph);
   float f = (ph - fi) + pl;
-  if (f < 0.0f) {
-    fi -= 1.0f;
-    f += 1.0f;
-  } else if (f >= 1.0f) {
-    fi += 1.0f;
-    f -= 1.0f;
-  }
-  const float top = (float)(N - 1);
-  if (fi > top) {
-    f += fi - top;
-    fi = top;
-  } else if (fi < 0.0f) {
-    f += fi;
-    fi = 0.0f;
-  }
-  fr = f;
-  return (uint32_t)fi;
+  const float df = floorf(f);
+  const float ip = fi + df;
+  f = f - df;
+  const float ipc = __builtin_amdgcn_fmed3f(ip, 0.0f, top);
+  fr = f + (ip - ipc);
+  return (uint32_t)ipc;
+}
+
+// Buffer resource over the whole [L][T][2] table (32-bit byte offsets;
+// out-of-range offsets read as zero instead of faulting).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const FieldDev& F) {
+  const uint32_t bytes = (F.L * (F.Tmask + 1u)) * (F.table_f16 ? 4u : 8u);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(F.tables), 0, (int)bytes, 0x00020000);
 }
 
 // Lane (sample, level group g) encodes levels g, g+4, g+8, g+12 of one point.
 // Levels with LOD weight 0 are not fetched.  feat[2j + f] = level g + 4j,
-// feature f.
+// feature f.  dense_mask (bit l: level l is stored densely) lets a group of
+// four levels that is all hashed (or all dense) use one index formula.
 template <bool TAB16>
-__device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* lv, const float x[3],
-                                             float lstar, bool active, int g, float feat[8],
+__device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* lv, __amdgpu_buffer_rsrc_t tab,
+                                             const float x[3], float lstar, bool active, int g, float feat[8],
                                              uint32_t& fetches) {
   float uh[3], ul[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) two_diff(x[a], F.amin[a], uh[a], ul[a]);
   const uint32_t T = F.Tmask + 1u;
+  constexpr uint32_t kShift = TAB16 ? 2u : 3u;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     feat[2 * j] = 0.0f;
     feat[2 * j + 1] = 0.0f;
     const int lev = g + 4 * j;
     if (!active || lev >= (int)F.L) continue;
-    const float w = F.lod ? fminf(fmaxf(lstar + 1.0f - (float)lev, 0.0f), 1.0f) : 1.0f;
+    const float w = F.lod ? __builtin_amdgcn_fmed3f(lstar + 1.0f - (float)lev, 0.0f, 1.0f) : 1.0f;
     if (!(w > 0.0f)) continue;
     const LevelDev P = lv[lev];
+    const float top = (float)(P.N - 1u);
     float fr[3];
     uint32_t i0[3];
-    i0[0] = base_corner(uh[0], ul[0], P.s_hi, P.s_lo, P.N, fr[0]);
-    i0[1] = base_corner(uh[1], ul[1], P.s_hi, P.s_lo, P.N, fr[1]);
-    i0[2] = base_corner(uh[2], ul[2], P.s_hi, P.s_lo, P.N, fr[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) i0[a] = base_corner(uh[a], ul[a], P.s_hi, P.s_lo, top, fr[a]);
     const uint32_t ax0 = i0[0] * P.mx, ax1 = ax0 + P.mx;
     const uint32_t ay0 = i0[1] * P.my, ay1 = ay0 + P.my;
     const uint32_t az0 = i0[2] * P.mz, az1 = az0 + P.mz;
+    const uint32_t grp = (F.dense_mask >> (4 * j)) & 0xFu;   // wave-uniform
     uint32_t idx[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const uint32_t a = (c & 1) ? ax1 : ax0, b = (c & 2) ? ay1 : ay0, e = (c & 4) ? az1 : az0;
-      idx[c] = P.dense ? (a + b + e) : ((a ^ b ^ e) & F.Tmask);
+      if (grp == 0u) idx[c] = (a ^ b ^ e) & F.Tmask;
+      else if (grp == 0xFu) idx[c] = a + b + e;
+      else idx[c] = P.dense ? (a + b + e) : ((a ^ b ^ e) & F.Tmask);
     }
+    const uint32_t base = ((uint32_t)lev * T) << kShift;
     float v0[8], v1[8];
     if (TAB16) {
-      const uint32_t* tab = reinterpret_cast<const uint32_t*>(F.tables) + (size_t)lev * T;
       uint32_t raw[8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) raw[c] = tab[idx[c]];
+      for (int c = 0; c < 8; ++c) raw[c] = __builtin_amdgcn_raw_buffer_load_b32(tab, (int)(base + (idx[c] << kShift)), 0, 0);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        _Float16 h0, h1;
-        const uint16_t lo16 = (uint16_t)(raw[c] & 0xFFFFu), hi16 = (uint16_t)(raw[c] >> 16);
-        __builtin_memcpy(&h0, &lo16, 2);
-        __builtin_memcpy(&h1, &hi16, 2);
-        v0[c] = (float)h0;
-        v1[c] = (float)h1;
+        v0[c] = (float)__builtin_bit_cast(_Float16, (uint16_t)(raw[c] & 0xFFFFu));
+        v1[c] = (float)__builtin_bit_cast(_Float16, (uint16_t)(raw[c] >> 16));
       }
     } else {
-      const float2* tab = reinterpret_cast<const float2*>(F.tables) + (size_t)lev * T;
-      float2 raw[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) raw[c] = tab[idx[c]];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        v0[c] = raw[c].x;
-        v1[c] = raw[c].y;
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b64(tab, (int)(base + (idx[c] << kShift)), 0, 0);
+        v0[c] = __builtin_bit_cast(float, (uint32_t)raw[0]);
+        v1[c] = __builtin_bit_cast(float, (uint32_t)raw[1]);
       }
     }
     const float wx[2] = {1.0f - fr[0], fr[0]};
@@ -432,14 +452,17 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
   v4f h[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) h[ot] = zero4();
-  for (uint32_t s4 = 0; s4 < d1_groups; ++s4) {
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) {
-      const float4 w = sw[kW32_D1 / 4 + (ot * 2 + s4) * 64 + lane];
-      h[ot] = mfma_f32(w.x, feat[4 * s4 + 0], h[ot]);
-      h[ot] = mfma_f32(w.y, feat[4 * s4 + 1], h[ot]);
-      h[ot] = mfma_f32(w.z, feat[4 * s4 + 2], h[ot]);
-      h[ot] = mfma_f32(w.w, feat[4 * s4 + 3], h[ot]);
+  for (int s4 = 0; s4 < 2; ++s4) {
+    if ((uint32_t)s4 < d1_groups) {
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        const float4 w = sw[kW32_D1 / 4 + (ot * 2 + s4) * 64 + lane];
+        h[ot] = mfma_f32(w.x, feat[4 * s4 + 0], h[ot]);
+        h[ot] = mfma_f32(w.y, feat[4 * s4 + 1], h[ot]);
+        h[ot] = mfma_f32(w.z, feat[4 * s4 + 2], h[ot]);
+        h[ot] = mfma_f32(w.w, feat[4 * s4 + 3], h[ot]);
+      }
     }
   }
 #pragma unroll
@@ -526,6 +549,23 @@ struct Half8 {
     }
     return r;
   }
+  __device__ static __forceinline__ uint16_t bits(float f) {
+    if constexpr (BF) return bf16_bits_rne(f);
+    else return __builtin_bit_cast(uint16_t, (_Float16)f);
+  }
+  // four values rounded to the element type, packed two per 32-bit word
+  __device__ static __forceinline__ uint2 pack4(const float* v) {
+    return make_uint2((uint32_t)bits(v[0]) | ((uint32_t)bits(v[1]) << 16),
+                      (uint32_t)bits(v[2]) | ((uint32_t)bits(v[3]) << 16));
+  }
+  // first four elements from floats, last four already packed
+  __device__ static __forceinline__ vec pack4_raw(const float* v, uint2 raw) {
+    const uint2 lo = pack4(v);
+    const uint4 u = make_uint4(lo.x, lo.y, raw.x, raw.y);
+    vec r;
+    __builtin_memcpy(&r, &u, 16);
+    return r;
+  }
   __device__ static __forceinline__ v4f mfma(vec a, vec b, v4f c) {
     if constexpr (BF) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     else return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -534,8 +574,7 @@ struct Half8 {
 
 template <bool BF>
 __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const float* __restrict__ sb,
-                                            const float feat[8], const float shs[4], int lane,
-                                            float& o0, float lg[3]) {
+                                            const float feat[8], uint2 shh, int lane, float& o0, float lg[3]) {
   typedef Half8<BF> H;
   typedef typename H::vec vec;
   const int g = lane >> 4;
@@ -558,8 +597,8 @@ __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const 
   o = H::mfma(wfrag(kW16_D2, 0), H::pack(hv), o);
   o = H::mfma(wfrag(kW16_D2, 1), H::pack(hv + 8), o);
   o = add_bias4(o, sb, kB2, g);
-  float cin[8] = {o[0], o[1], o[2], o[3], shs[0], shs[1], shs[2], shs[3]};
-  const vec cv = H::pack(cin);
+  const float oo[4] = {o[0], o[1], o[2], o[3]};
+  const vec cv = H::pack4_raw(oo, shh);
   v4f c1[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) c1[ot] = add_bias4(H::mfma(wfrag(kW16_C1, ot), cv, zero4()), sb, kB3 + 16 * ot, g);
@@ -588,6 +627,92 @@ __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const 
   lg[0] = c3[0];
   lg[1] = c3[1];
   lg[2] = c3[2];
+}
+
+// The 16-bit MLPs over up to four 16-sample tiles at once: every weight
+// fragment is read from LDS once per call and applied to all tiles, so LDS
+// traffic for weights falls by the number of tiles.  nt is wave-uniform.
+template <bool BF, int NB>
+__device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const float* __restrict__ sb, int nt,
+                                             const typename Half8<BF>::vec xin[NB], const uint2 shh[NB],
+                                             int lane, float o0[NB], float lg[NB][3]) {
+  typedef Half8<BF> H;
+  typedef typename H::vec vec;
+  const int g = lane >> 4;
+  auto wfrag = [&](int off16, int idx) -> vec {
+    const uint4 u = sw[off16 / 8 + idx * 64 + lane];
+    vec v;
+    __builtin_memcpy(&v, &u, 16);
+    return v;
+  };
+  // one 64-wide hidden layer fed by a single 32-deep B operand per tile;
+  // output tiles are produced in pairs so only packed halves stay live
+  auto layer_k32 = [&](int off16, int boff, const vec* in, vec out[NB][2]) {
+#pragma unroll
+    for (int pair = 0; pair < 2; ++pair) {
+      const vec w0 = wfrag(off16, 2 * pair), w1 = wfrag(off16, 2 * pair + 1);
+#pragma unroll
+      for (int t = 0; t < NB; ++t)
+        if (t < nt) {
+          const v4f a = add_bias4(H::mfma(w0, in[t], zero4()), sb, boff + 32 * pair, g);
+          const v4f b = add_bias4(H::mfma(w1, in[t], zero4()), sb, boff + 32 * pair + 16, g);
+          const float hv[8] = {fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f),
+                               fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f)};
+          out[t][pair] = H::pack(hv);
+        }
+    }
+  };
+  vec hp[NB][2];
+  layer_k32(kW16_D1, kB1, xin, hp);
+  v4f o[NB];
+  {
+    const vec w0 = wfrag(kW16_D2, 0), w1 = wfrag(kW16_D2, 1);
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t < nt) o[t] = add_bias4(H::mfma(w1, hp[t][1], H::mfma(w0, hp[t][0], zero4())), sb, kB2, g);
+  }
+  vec cv[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t)
+    if (t < nt) {
+      const float oo[4] = {o[t][0], o[t][1], o[t][2], o[t][3]};
+      cv[t] = H::pack4_raw(oo, shh[t]);
+    }
+  vec c1p[NB][2];
+  layer_k32(kW16_C1, kB3, cv, c1p);
+  vec c2p[NB][2];
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    const vec wa0 = wfrag(kW16_C2, 4 * pair + 0), wa1 = wfrag(kW16_C2, 4 * pair + 1);
+    const vec wb0 = wfrag(kW16_C2, 4 * pair + 2), wb1 = wfrag(kW16_C2, 4 * pair + 3);
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t < nt) {
+        const v4f a = add_bias4(H::mfma(wa1, c1p[t][1], H::mfma(wa0, c1p[t][0], zero4())), sb,
+                                kB4 + 32 * pair, g);
+        const v4f b = add_bias4(H::mfma(wb1, c1p[t][1], H::mfma(wb0, c1p[t][0], zero4())), sb,
+                                kB4 + 32 * pair + 16, g);
+        const float hv[8] = {fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f),
+                             fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f)};
+        c2p[t][pair] = H::pack(hv);
+      }
+  }
+  v4f c3[NB];
+  {
+    const vec w0 = wfrag(kW16_C3, 0), w1 = wfrag(kW16_C3, 1);
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t < nt) c3[t] = H::mfma(w1, c2p[t][1], H::mfma(w0, c2p[t][0], zero4()));
+  }
+#pragma unroll
+  for (int t = 0; t < NB; ++t)
+    if (t < nt) {
+      c3[t] = add_bias4(c3[t], sb, kB5, g);
+      o0[t] = o[t][0];
+      lg[t][0] = c3[t][0];
+      lg[t][1] = c3[t][1];
+      lg[t][2] = c3[t][2];
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -14,6 +14,8 @@ constexpr int kQueues = 8;          // one ray queue per XCD
 constexpr int kTile = 8;            // rays are issued in 8x8 pixel tiles
 constexpr int kBlock = 256;         // threads per render block (4 waves)
 constexpr int kHidden = 64;
+constexpr int kCoarseWords = 1024;  // <= 32^3 bits of coarse occupancy in LDS
+constexpr int kMlpBatch = 1;        // 16-sample tiles per 16-bit MLP call (weights read once per call)
 
 // MFMA fragment layout of the MLP weights (see mlp_tile in device.hpp).
 // FP32: [layer][out_tile][kstep/4][lane][4]; FP16/BF16: [layer][out_tile][kstep][lane][8].
@@ -35,20 +37,21 @@ struct LevelDev {
 struct FieldDev {
   const void* tables;        // [L][T][2] fp32 or fp16
   const LevelDev* levels;    // [L]
-  const uint32_t* occ;       // G^3 bits
-  const uint32_t* occ_coarse;// Gc^3 bits, block = 2^bshift cells
+  const unsigned long long* bricks;  // Gb^3 bricks of 4x4x4 cells, bit (x&3) + 4 (y&3) + 16 (z&3)
+  const uint32_t* coarse;    // Gc^3 bits (Gc <= 32), block = 2^cshift cells; staged in LDS
   const float* w32;          // kW32Total
   const uint16_t* w16;       // kW16Total fp16 bits
   const uint16_t* wbf;       // kW16Total bf16 bits
   const float* bias;         // kBiasTotal
   uint32_t L, log2T, Tmask, table_f16;
-  uint32_t G, Gc, bshift, nsh;
+  uint32_t G, Gb, Gc, cshift, nsh;
   float amin[3], cs;         // cs = fp32(G / extent)
   float dt, t_min, extent, inv_ln_f;
   uint32_t max_samples;
   int32_t lod;
   float lod_c;               // ln(2 s / extent)
   float lod_bias, lod_radius_scale;
+  uint32_t dense_mask;       // bit l set: level l is stored densely
   uint32_t d1_ksteps;        // FP32 k-steps of the first density layer
   uint32_t c1_ksteps;        // FP32 k-steps of the first color layer
 };
@@ -56,7 +59,7 @@ struct FieldDev {
 // Workspace layout (bytes).  Counters are spaced 64 B apart.
 constexpr int kWsQueue = 0;        // kQueues x u32 at stride 16 u32
 constexpr int kWsDone = 512;       // u32 blocks-finished counter
-constexpr int kWsStats = 576;      // 4 x u64
+constexpr int kWsStats = 576;      // 6 x u64: rays, samples, level fetches, march steps, rounds, tiles
 constexpr int kWsCams = 640;       // kMaxCams x vrn_camera
 constexpr int kWsBytes = 4096;
 

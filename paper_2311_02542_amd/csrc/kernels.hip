@@ -53,22 +53,65 @@ __device__ __forceinline__ void run_mlp(const uint8_t* s_w, const float* s_b, co
   if constexpr (MODE == 0)
     mlp_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, shs, lane, o0, lg);
   else
-    mlp_tile_16<MODE == 2>(reinterpret_cast<const uint4*>(s_w), s_b, feat, shs, lane, o0, lg);
+    mlp_tile_16<MODE == 2>(reinterpret_cast<const uint4*>(s_w), s_b, feat, Half8<MODE == 2>::pack4(shs), lane,
+                           o0, lg);
+}
+
+// Stage the coarse occupancy grid into LDS.
+__device__ __forceinline__ void load_coarse(const FieldDev& F, uint32_t* s_coarse) {
+  const uint32_t words = (F.Gc * F.Gc * F.Gc + 31u) / 32u;
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) s_coarse[i] = F.coarse[i];
+}
+
+// The lane that owns the s-th compacted sample (s = 16 t + (lane & 15)).
+__device__ __forceinline__ int tile_source(uint64_t m, int ns, int t, int lane, bool& act) {
+  const int s = t * 16 + (lane & 15);
+  act = s < ns;
+  return act ? nth_set_bit(m, s) : lane;
+}
+
+// Gather a compacted sample's position and LOD level from its owner lane and
+// encode it (4 lanes per sample, one level group each).
+template <bool TAB16>
+__device__ __forceinline__ void tile_encode(const FieldDev& F, const LevelDev* s_lv, __amdgpu_buffer_rsrc_t tab,
+                                            int src, bool act, int lane, const float sx[3], float slst,
+                                            float feat[8], uint32_t& fetches) {
+  const float px[3] = {shfl_f(sx[0], src), shfl_f(sx[1], src), shfl_f(sx[2], src)};
+  const float lstar = shfl_f(slst, src);
+  encode_point<TAB16>(F, s_lv, tab, px, lstar, act, lane >> 4, feat, fetches);
+}
+
+// Per-ray SH values in the MFMA element type, laid out [lane][group g][c = g + 4 i].
+template <bool BF>
+__device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, uint2* s_sh_lane) {
+  float s[16];
+  sh_basis16(r.dx, r.dy, r.dz, s);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (uint32_t)(g + 4 * i) < F.nsh ? s[g + 4 * i] : 0.0f;
+    s_sh_lane[g] = Half8<BF>::pack4(v);
+  }
 }
 
 template <bool TAB16, int MODE>
-__global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs A) {
+__global__ __launch_bounds__(kBlock, 4) void render_kernel(RenderArgs A) {
   __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
   __shared__ float s_b[kBiasTotal];
   __shared__ LevelDev s_lv[kMaxLevels];
+  __shared__ uint32_t s_coarse[kCoarseWords];
   __shared__ uint32_t s_off[kMaxCams + 1];
   __shared__ uint32_t s_rb[kMaxCams], s_re[kMaxCams];
-  __shared__ uint32_t s_stats[4];
+  __shared__ uint32_t s_stats[6];
+  __shared__ uint2 s_sh[MODE == 0 ? 1 : kBlock * 4];
 
   const FieldDev& F = A.F;
+  const __amdgpu_buffer_rsrc_t tab = table_rsrc(F);
   load_weights<MODE>(F, s_w, s_b);
+  load_coarse(F, s_coarse);
   if (threadIdx.x < F.L) s_lv[threadIdx.x] = F.levels[threadIdx.x];
-  if (threadIdx.x < 4) s_stats[threadIdx.x] = 0;
+  if (threadIdx.x < 6) s_stats[threadIdx.x] = 0;
   const uint32_t tx = (A.W + kTile - 1) / kTile;
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
@@ -85,7 +128,6 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs A) {
   __syncthreads();
 
   const int lane = lane_id();
-  const int g = lane >> 4;
   const uint32_t n_tiles = s_off[A.n_cams] / (kTile * kTile);
   uint32_t* ctrl = reinterpret_cast<uint32_t*>(A.ws + kWsQueue);
   int q = (int)(blockIdx.x % kQueues);
@@ -96,10 +138,13 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs A) {
   r.k = 0;
   r.k_hi = -1;
   r.lr = 0.0f;
+  r.brick = -1;
+  r.blo = r.bhi = 0u;
+  r.delta = 0.0f;
   r.ox = r.oy = r.oz = r.dx = r.dy = r.dz = 0.0f;
   uint32_t pix = kNone, n = 0;
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-  uint32_t st_steps = 0, st_fetch = 0, st_samples = 0, st_rays = 0;
+  uint32_t st_steps = 0, st_fetch = 0, st_samples = 0, st_rays = 0, st_rounds = 0, st_tiles = 0;
 
   auto retire = [&]() {
     float4 v = make_float4(cr, cg, cb, 1.0f - T);
@@ -115,6 +160,9 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs A) {
   };
 
   while (true) {
+    // keep LDS reads of weights inside the loop (hoisting would pin the
+    // weights in registers and drop occupancy to one wave per SIMD)
+    asm volatile("" ::: "memory");
     // ---- 1. refill lanes that have no ray -------------------------------
     while (!out_of_work) {
       const uint64_t need = __ballot(pix == kNone);
@@ -138,6 +186,7 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs A) {
           const uint32_t row = s_rb[c] + (tile / tx) * kTile + within / kTile;
           if (col < A.W && row < s_re[c]) {
             setup_ray(F, A.cams[c], col, row, r);
+            if constexpr (MODE != 0) store_ray_sh<MODE == 2>(F, r, &s_sh[threadIdx.x * 4]);
             pix = (c * A.H + row) * A.W + col;
             T = 1.0f;
             cr = cg = cb = 0.0f;
@@ -151,46 +200,81 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs A) {
       }
     }
     if (__ballot(pix != kNone) == 0) break;
+    __builtin_amdgcn_wave_barrier();
 
     // ---- 2. march to the next evaluated sample ---------------------------
     int mres = 0;
-    float st = 0.0f, sx[3] = {0.0f, 0.0f, 0.0f};
+    float st = 0.0f, sx[3] = {0.0f, 0.0f, 0.0f}, slst = 0.0f;
     if (pix != kNone) {
-      mres = march_next(F, r, A.budget, st_steps, st, sx);
+      mres = march_next(F, s_coarse, r, A.budget, st_steps, st, sx);
       if (mres == 2) retire();
+      if (mres == 1 && F.lod) slst = level_star(F, st, r.lr);
     }
     const bool has = mres == 1;
     const uint64_t m = __ballot(has);
     const int ns = __popcll(m);
     const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    const int nt = (ns + 15) >> 4;
+    if (lane == 0) {
+      ++st_rounds;
+      st_tiles += (uint32_t)nt;
+    }
 
-    // ---- 3. encode + MLP, 16 samples per tile -----------------------------
+    // ---- 3. encode + MLP of the compacted samples -------------------------
     float so0 = 0.0f, sl0 = 0.0f, sl1 = 0.0f, sl2 = 0.0f;
-    for (int t = 0; t * 16 < ns; ++t) {
-      // keep the LDS weight reads inside the loop (hoisting them would pin
-      // ~10k weights in registers and drop occupancy to one wave per SIMD)
-      asm volatile("" ::: "memory");
-      const int s = t * 16 + (lane & 15);
-      const bool act = s < ns;
-      const int src = act ? nth_set_bit(m, s) : lane;
-      const float px[3] = {shfl_f(sx[0], src), shfl_f(sx[1], src), shfl_f(sx[2], src)};
-      const float pt = shfl_f(st, src), plr = shfl_f(r.lr, src);
-      const float pdx = shfl_f(r.dx, src), pdy = shfl_f(r.dy, src), pdz = shfl_f(r.dz, src);
-      float feat[8];
-      const float lstar = F.lod ? level_star(F, pt, plr) : 0.0f;
-      encode_point<TAB16>(F, s_lv, px, lstar, act, g, feat, st_fetch);
-      float shs[4];
-      sh_select(F, pdx, pdy, pdz, g, shs);
-      float o0, lg[3];
-      run_mlp<MODE>(s_w, s_b, F, feat, shs, lane, o0, lg);
-      const int from = rank & 15;
-      const float a0 = shfl_f(o0, from), a1 = shfl_f(lg[0], from);
-      const float a2 = shfl_f(lg[1], from), a3 = shfl_f(lg[2], from);
-      if (has && (rank >> 4) == t) {
-        so0 = a0;
-        sl0 = a1;
-        sl1 = a2;
-        sl2 = a3;
+    const int wave_base = (threadIdx.x >> 6) << 6;
+    if constexpr (MODE == 0) {
+      for (int t = 0; t < nt; ++t) {
+        asm volatile("" ::: "memory");
+        bool act;
+        const int src = tile_source(m, ns, t, lane, act);
+        float feat[8], shs[4];
+        tile_encode<TAB16>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
+        sh_select(F, shfl_f(r.dx, src), shfl_f(r.dy, src), shfl_f(r.dz, src), lane >> 4, shs);
+        float o0, lg[3];
+        mlp_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, shs, lane, o0, lg);
+        const int from = rank & 15;
+        const float a0 = shfl_f(o0, from), a1 = shfl_f(lg[0], from);
+        const float a2 = shfl_f(lg[1], from), a3 = shfl_f(lg[2], from);
+        if (has && (rank >> 4) == t) {
+          so0 = a0;
+          sl0 = a1;
+          sl1 = a2;
+          sl2 = a3;
+        }
+      }
+    } else {
+      typedef Half8<MODE == 2> H;
+      for (int t0 = 0; t0 < nt; t0 += kMlpBatch) {
+        asm volatile("" ::: "memory");
+        const int cnt = min(kMlpBatch, nt - t0);
+        typename H::vec xin[kMlpBatch];
+        uint2 shh[kMlpBatch];
+#pragma unroll
+        for (int t = 0; t < kMlpBatch; ++t)
+          if (t < cnt) {
+            bool act;
+            const int src = tile_source(m, ns, t0 + t, lane, act);
+            float feat[8];
+            tile_encode<TAB16>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
+            xin[t] = H::pack(feat);
+            shh[t] = s_sh[(wave_base + src) * 4 + (lane >> 4)];
+          }
+        float o0[kMlpBatch], lg[kMlpBatch][3];
+        mlp_batch_16<MODE == 2, kMlpBatch>(reinterpret_cast<const uint4*>(s_w), s_b, cnt, xin, shh, lane, o0, lg);
+        const int from = rank & 15;
+#pragma unroll
+        for (int t = 0; t < kMlpBatch; ++t)
+          if (t < cnt) {
+            const float a0 = shfl_f(o0[t], from), a1 = shfl_f(lg[t][0], from);
+            const float a2 = shfl_f(lg[t][1], from), a3 = shfl_f(lg[t][2], from);
+            if (has && (rank >> 4) == t0 + t) {
+              so0 = a0;
+              sl0 = a1;
+              sl1 = a2;
+              sl2 = a3;
+            }
+          }
       }
     }
 
@@ -213,10 +297,12 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs A) {
   atomicAdd(&s_stats[1], st_samples);
   atomicAdd(&s_stats[2], st_fetch);
   atomicAdd(&s_stats[3], st_steps);
+  atomicAdd(&s_stats[4], st_rounds);
+  atomicAdd(&s_stats[5], st_tiles);
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long* stats = reinterpret_cast<unsigned long long*>(A.ws + kWsStats);
-    for (int i = 0; i < 4; ++i) atomicAdd(&stats[i], (unsigned long long)s_stats[i]);
+    for (int i = 0; i < 6; ++i) atomicAdd(&stats[i], (unsigned long long)s_stats[i]);
     __threadfence();
     uint32_t* done = reinterpret_cast<uint32_t*>(A.ws + kWsDone);
     if (atomicAdd(done, 1u) == gridDim.x - 1) {
@@ -255,6 +341,9 @@ __global__ void rays_kernel(const vrn_camera* cams, uint32_t n_cams, uint32_t W,
 
 __global__ void march_kernel(FieldDev F, const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H,
                              uint32_t* klist, uint32_t max_k, uint32_t* count) {
+  __shared__ uint32_t s_coarse[kCoarseWords];
+  load_coarse(F, s_coarse);
+  __syncthreads();
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i >= (uint64_t)n_cams * W * H) return;
   const uint32_t c = (uint32_t)(i / ((uint64_t)W * H));
@@ -264,7 +353,7 @@ __global__ void march_kernel(FieldDev F, const vrn_camera* cams, uint32_t n_cams
   uint32_t cnt = 0, steps = 0;
   float st, sx[3];
   while (cnt < F.max_samples) {
-    if (march_next(F, r, 0x40000000u, steps, st, sx) != 1) break;
+    if (march_next(F, s_coarse, r, 0x40000000u, steps, st, sx) != 1) break;
     if (cnt < max_k) klist[i * max_k + cnt] = (uint32_t)(r.k - 1);
     ++cnt;
   }
@@ -287,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void encode_kernel(FieldDev F, const float*
   }
   float f[8];
   uint32_t fetches = 0;
-  encode_point<TAB16>(F, s_lv, x, lstar, act, g, f, fetches);
+  encode_point<TAB16>(F, s_lv, table_rsrc(F), x, lstar, act, g, f, fetches);
   if (!act) return;
   for (int j = 0; j < 4; ++j) {
     const int lev = g + 4 * j;
