@@ -413,6 +413,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   for (int a = 0; a < 3; ++a) F.amin[a] = d->aabb_min[a];
   F.cs = (float)((double)G / (double)d->extent);
   F.dt = d->dt;
+  F.inv_dt = (float)(1.0 / (double)d->dt);
+  F.inv_cs = (float)((double)d->extent / (double)G);
   F.t_min = d->t_min;
   F.extent = d->extent;
   F.max_samples = d->max_samples;

@@ -94,7 +94,8 @@ __device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
   for (int a = 0; a < 3; ++a) {
     const float lo = F.amin[a], hi = F.amin[a] + F.extent;
     if (d[a] != 0.0f) {
-      const float t1 = (lo - o[a]) / d[a], t2 = (hi - o[a]) / d[a];
+      const float id = __builtin_amdgcn_rcpf(d[a]);
+      const float t1 = (lo - o[a]) * id, t2 = (hi - o[a]) * id;
       tn = fmaxf(tn, fminf(t1, t2));
       tf = fminf(tf, fmaxf(t1, t2));
     } else if (o[a] < lo || o[a] > hi) {
@@ -102,8 +103,8 @@ __device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
     }
   }
   const float kmax = 16777000.0f;  // keep k < 2^24 (k + 0.5 exact in FP32)
-  const float klo = floorf(tn / F.dt - 0.5f) - 2.0f;
-  const float khi = ceilf(fminf(tf / F.dt, kmax) - 0.5f) + 2.0f;
+  const float klo = floorf(tn * F.inv_dt - 0.5f) - 2.0f;
+  const float khi = ceilf(fminf(tf * F.inv_dt, kmax) - 0.5f) + 2.0f;
   if (miss || !(tf >= tn - 2.0f * F.dt) || klo > kmax) {
     r.k = 0;
     r.k_hi = -1;
@@ -169,13 +170,15 @@ __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float 
     return false;
   const float o[3] = {r.ox, r.oy, r.oz};
   const float d[3] = {r.dx, r.dy, r.dz};
+  // approximate exit parameter (reciprocals need not be exact: the landing
+  // sample is re-tested with the canonical arithmetic below)
   float te = 3.0e38f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float bq = signbit(d[a]) ? lo[a] : hi[a];
-    te = fminf(te, (bq / F.cs + F.amin[a] - o[a]) / d[a]);
+    te = fminf(te, (bq * F.inv_cs + F.amin[a] - o[a]) * __builtin_amdgcn_rcpf(d[a]));
   }
-  const float kbf = fminf(floorf(te / F.dt - 0.5f), (float)r.k_hi);
+  const float kbf = fminf(floorf(te * F.inv_dt - 0.5f), (float)r.k_hi);
   if (!(kbf >= (float)r.k + 2.0f)) return false;
   int kb = (int)kbf;
 #pragma unroll
@@ -284,17 +287,32 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const FieldDev& F) 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(F.tables), 0, (int)bytes, 0x00020000);
 }
 
+// Base corner and fraction from a plain FP32 p = u * S (the 16-bit paths,
+// whose error budget is far above the rounding of p).
+__device__ __forceinline__ uint32_t base_corner_fast(float u, float shi, float top, float& fr) {
+  const float p = u * shi;
+  const float fi = floorf(p);
+  const float ipc = __builtin_amdgcn_fmed3f(fi, 0.0f, top);
+  fr = (p - fi) + (fi - ipc);
+  return (uint32_t)ipc;
+}
+
 // Lane (sample, level group g) encodes levels g, g+4, g+8, g+12 of one point.
 // Levels with LOD weight 0 are not fetched.  feat[2j + f] = level g + 4j,
 // feature f.  dense_mask (bit l: level l is stored densely) lets a group of
 // four levels that is all hashed (or all dense) use one index formula.
-template <bool TAB16>
+// PRECISE selects the double-float lattice coordinate (FP32 path and the
+// encode stage entry point).
+template <bool TAB16, bool PRECISE>
 __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* lv, __amdgpu_buffer_rsrc_t tab,
                                              const float x[3], float lstar, bool active, int g, float feat[8],
                                              uint32_t& fetches) {
   float uh[3], ul[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) two_diff(x[a], F.amin[a], uh[a], ul[a]);
+  for (int a = 0; a < 3; ++a) {
+    if constexpr (PRECISE) two_diff(x[a], F.amin[a], uh[a], ul[a]);
+    else uh[a] = x[a] - F.amin[a];
+  }
   const uint32_t T = F.Tmask + 1u;
   constexpr uint32_t kShift = TAB16 ? 2u : 3u;
 #pragma unroll
@@ -310,25 +328,40 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     float fr[3];
     uint32_t i0[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) i0[a] = base_corner(uh[a], ul[a], P.s_hi, P.s_lo, top, fr[a]);
-    const uint32_t ax0 = i0[0] * P.mx, ax1 = ax0 + P.mx;
-    const uint32_t ay0 = i0[1] * P.my, ay1 = ay0 + P.my;
-    const uint32_t az0 = i0[2] * P.mz, az1 = az0 + P.mz;
-    const uint32_t grp = (F.dense_mask >> (4 * j)) & 0xFu;   // wave-uniform
-    uint32_t idx[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const uint32_t a = (c & 1) ? ax1 : ax0, b = (c & 2) ? ay1 : ay0, e = (c & 4) ? az1 : az0;
-      if (grp == 0u) idx[c] = (a ^ b ^ e) & F.Tmask;
-      else if (grp == 0xFu) idx[c] = a + b + e;
-      else idx[c] = P.dense ? (a + b + e) : ((a ^ b ^ e) & F.Tmask);
+    for (int a = 0; a < 3; ++a) {
+      if constexpr (PRECISE) i0[a] = base_corner(uh[a], ul[a], P.s_hi, P.s_lo, top, fr[a]);
+      else i0[a] = base_corner_fast(uh[a], P.s_hi, top, fr[a]);
     }
+    const uint32_t grp = (F.dense_mask >> (4 * j)) & 0xFu;   // wave-uniform
     const uint32_t base = ((uint32_t)lev * T) << kShift;
+    uint32_t off[8];
+    if (grp == 0u) {
+      // hashed: byte offset = base + ((hx ^ hy ^ hz) & mask) << shift, with the
+      // mask and shift folded into the per-axis terms
+      const uint32_t m = F.Tmask << kShift;
+      const uint32_t hx0 = (i0[0] * P.mx) << kShift, hx1 = hx0 + (P.mx << kShift);
+      const uint32_t hy0 = (i0[1] * P.my) << kShift, hy1 = hy0 + (P.my << kShift);
+      const uint32_t hz0 = (i0[2] * P.mz) << kShift, hz1 = hz0 + (P.mz << kShift);
+      const uint32_t x0 = hx0 & m, x1 = hx1 & m, y0 = hy0 & m, y1 = hy1 & m, z0 = hz0 & m, z1 = hz1 & m;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        off[c] = base + (((c & 1) ? x1 : x0) ^ ((c & 2) ? y1 : y0) ^ ((c & 4) ? z1 : z0));
+    } else {
+      const uint32_t ax0 = i0[0] * P.mx, ax1 = ax0 + P.mx;
+      const uint32_t ay0 = i0[1] * P.my, ay1 = ay0 + P.my;
+      const uint32_t az0 = i0[2] * P.mz, az1 = az0 + P.mz;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const uint32_t a = (c & 1) ? ax1 : ax0, b = (c & 2) ? ay1 : ay0, e = (c & 4) ? az1 : az0;
+        const uint32_t idx = (grp == 0xFu || P.dense) ? (a + b + e) : ((a ^ b ^ e) & F.Tmask);
+        off[c] = base + (idx << kShift);
+      }
+    }
     float v0[8], v1[8];
     if (TAB16) {
       uint32_t raw[8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) raw[c] = __builtin_amdgcn_raw_buffer_load_b32(tab, (int)(base + (idx[c] << kShift)), 0, 0);
+      for (int c = 0; c < 8; ++c) raw[c] = __builtin_amdgcn_raw_buffer_load_b32(tab, (int)off[c], 0, 0);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         v0[c] = (float)__builtin_bit_cast(_Float16, (uint16_t)(raw[c] & 0xFFFFu));
@@ -337,7 +370,7 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     } else {
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const auto raw = __builtin_amdgcn_raw_buffer_load_b64(tab, (int)(base + (idx[c] << kShift)), 0, 0);
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b64(tab, (int)off[c], 0, 0);
         v0[c] = __builtin_bit_cast(float, (uint32_t)raw[0]);
         v1[c] = __builtin_bit_cast(float, (uint32_t)raw[1]);
       }
@@ -434,6 +467,18 @@ __device__ __forceinline__ v4f add_bias4(v4f v, const float* sb, int base, int g
   v4f r;
 #pragma unroll
   for (int i = 0; i < 4; ++i) r[i] = v[i] + sb[base + 4 * g + i];
+  return r;
+}
+
+// The 16-bit paths start the FP32 accumulator at the bias (one 16-byte LDS
+// read, no adds); the FP32 path adds it after accumulation for accuracy.
+__device__ __forceinline__ v4f bias_acc(const float* sb, int base, int g) {
+  const float4 b = *reinterpret_cast<const float4*>(sb + base + 4 * g);
+  v4f r;
+  r[0] = b.x;
+  r[1] = b.y;
+  r[2] = b.z;
+  r[3] = b.w;
   return r;
 }
 
@@ -654,8 +699,8 @@ __device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const
 #pragma unroll
       for (int t = 0; t < NB; ++t)
         if (t < nt) {
-          const v4f a = add_bias4(H::mfma(w0, in[t], zero4()), sb, boff + 32 * pair, g);
-          const v4f b = add_bias4(H::mfma(w1, in[t], zero4()), sb, boff + 32 * pair + 16, g);
+          const v4f a = H::mfma(w0, in[t], bias_acc(sb, boff + 32 * pair, g));
+          const v4f b = H::mfma(w1, in[t], bias_acc(sb, boff + 32 * pair + 16, g));
           const float hv[8] = {fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f),
                                fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f)};
           out[t][pair] = H::pack(hv);
@@ -669,7 +714,7 @@ __device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const
     const vec w0 = wfrag(kW16_D2, 0), w1 = wfrag(kW16_D2, 1);
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      if (t < nt) o[t] = add_bias4(H::mfma(w1, hp[t][1], H::mfma(w0, hp[t][0], zero4())), sb, kB2, g);
+      if (t < nt) o[t] = H::mfma(w1, hp[t][1], H::mfma(w0, hp[t][0], bias_acc(sb, kB2, g)));
   }
   vec cv[NB];
 #pragma unroll
@@ -688,10 +733,8 @@ __device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const
 #pragma unroll
     for (int t = 0; t < NB; ++t)
       if (t < nt) {
-        const v4f a = add_bias4(H::mfma(wa1, c1p[t][1], H::mfma(wa0, c1p[t][0], zero4())), sb,
-                                kB4 + 32 * pair, g);
-        const v4f b = add_bias4(H::mfma(wb1, c1p[t][1], H::mfma(wb0, c1p[t][0], zero4())), sb,
-                                kB4 + 32 * pair + 16, g);
+        const v4f a = H::mfma(wa1, c1p[t][1], H::mfma(wa0, c1p[t][0], bias_acc(sb, kB4 + 32 * pair, g)));
+        const v4f b = H::mfma(wb1, c1p[t][1], H::mfma(wb0, c1p[t][0], bias_acc(sb, kB4 + 32 * pair + 16, g)));
         const float hv[8] = {fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f),
                              fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f)};
         c2p[t][pair] = H::pack(hv);
@@ -702,12 +745,11 @@ __device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const
     const vec w0 = wfrag(kW16_C3, 0), w1 = wfrag(kW16_C3, 1);
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      if (t < nt) c3[t] = H::mfma(w1, c2p[t][1], H::mfma(w0, c2p[t][0], zero4()));
+      if (t < nt) c3[t] = H::mfma(w1, c2p[t][1], H::mfma(w0, c2p[t][0], bias_acc(sb, kB5, g)));
   }
 #pragma unroll
   for (int t = 0; t < NB; ++t)
     if (t < nt) {
-      c3[t] = add_bias4(c3[t], sb, kB5, g);
       o0[t] = o[t][0];
       lg[t][0] = c3[t][0];
       lg[t][1] = c3[t][1];

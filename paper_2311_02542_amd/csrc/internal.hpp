@@ -47,6 +47,7 @@ struct FieldDev {
   uint32_t G, Gb, Gc, cshift, nsh;
   float amin[3], cs;         // cs = fp32(G / extent)
   float dt, t_min, extent, inv_ln_f;
+  float inv_dt, inv_cs;      // approximate reciprocals for skip estimates
   uint32_t max_samples;
   int32_t lod;
   float lod_c;               // ln(2 s / extent)

@@ -24,7 +24,7 @@ namespace vrn {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
+__device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + expf(-z)); }
 
 template <int MODE>
 struct WeightSmem {
@@ -63,22 +63,23 @@ __device__ __forceinline__ void load_coarse(const FieldDev& F, uint32_t* s_coars
   for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) s_coarse[i] = F.coarse[i];
 }
 
-// The lane that owns the s-th compacted sample (s = 16 t + (lane & 15)).
-__device__ __forceinline__ int tile_source(uint64_t m, int ns, int t, int lane, bool& act) {
+// The lane that owns compacted sample s = 16 t + (lane & 15), from the
+// wave's slot table in LDS.
+__device__ __forceinline__ int tile_source(const uint32_t* s_slot_w, int ns, int t, int lane, bool& act) {
   const int s = t * 16 + (lane & 15);
   act = s < ns;
-  return act ? nth_set_bit(m, s) : lane;
+  return act ? (int)s_slot_w[s] : lane;
 }
 
 // Gather a compacted sample's position and LOD level from its owner lane and
 // encode it (4 lanes per sample, one level group each).
-template <bool TAB16>
+template <bool TAB16, bool PRECISE>
 __device__ __forceinline__ void tile_encode(const FieldDev& F, const LevelDev* s_lv, __amdgpu_buffer_rsrc_t tab,
                                             int src, bool act, int lane, const float sx[3], float slst,
                                             float feat[8], uint32_t& fetches) {
   const float px[3] = {shfl_f(sx[0], src), shfl_f(sx[1], src), shfl_f(sx[2], src)};
   const float lstar = shfl_f(slst, src);
-  encode_point<TAB16>(F, s_lv, tab, px, lstar, act, lane >> 4, feat, fetches);
+  encode_point<TAB16, PRECISE>(F, s_lv, tab, px, lstar, act, lane >> 4, feat, fetches);
 }
 
 // Per-ray SH values in the MFMA element type, laid out [lane][group g][c = g + 4 i].
@@ -96,7 +97,7 @@ __device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, ui
 }
 
 template <bool TAB16, int MODE>
-__global__ __launch_bounds__(kBlock, 4) void render_kernel(RenderArgs A) {
+__global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(RenderArgs A) {
   __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
   __shared__ float s_b[kBiasTotal];
   __shared__ LevelDev s_lv[kMaxLevels];
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(kBlock, 4) void render_kernel(RenderArgs A) {
   __shared__ uint32_t s_rb[kMaxCams], s_re[kMaxCams];
   __shared__ uint32_t s_stats[6];
   __shared__ uint2 s_sh[MODE == 0 ? 1 : kBlock * 4];
+  __shared__ uint32_t s_slot[kBlock];
 
   const FieldDev& F = A.F;
   const __amdgpu_buffer_rsrc_t tab = table_rsrc(F);
@@ -215,6 +217,9 @@ __global__ __launch_bounds__(kBlock, 4) void render_kernel(RenderArgs A) {
     const int ns = __popcll(m);
     const int rank = __popcll(m & ((1ull << lane) - 1ull));
     const int nt = (ns + 15) >> 4;
+    const int wave_base = (threadIdx.x >> 6) << 6;
+    if (has) s_slot[wave_base + rank] = (uint32_t)lane;
+    __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
       ++st_rounds;
       st_tiles += (uint32_t)nt;
@@ -222,14 +227,13 @@ __global__ __launch_bounds__(kBlock, 4) void render_kernel(RenderArgs A) {
 
     // ---- 3. encode + MLP of the compacted samples -------------------------
     float so0 = 0.0f, sl0 = 0.0f, sl1 = 0.0f, sl2 = 0.0f;
-    const int wave_base = (threadIdx.x >> 6) << 6;
     if constexpr (MODE == 0) {
       for (int t = 0; t < nt; ++t) {
         asm volatile("" ::: "memory");
         bool act;
-        const int src = tile_source(m, ns, t, lane, act);
+        const int src = tile_source(&s_slot[wave_base], ns, t, lane, act);
         float feat[8], shs[4];
-        tile_encode<TAB16>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
+        tile_encode<TAB16, true>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
         sh_select(F, shfl_f(r.dx, src), shfl_f(r.dy, src), shfl_f(r.dz, src), lane >> 4, shs);
         float o0, lg[3];
         mlp_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, shs, lane, o0, lg);
@@ -254,9 +258,9 @@ __global__ __launch_bounds__(kBlock, 4) void render_kernel(RenderArgs A) {
         for (int t = 0; t < kMlpBatch; ++t)
           if (t < cnt) {
             bool act;
-            const int src = tile_source(m, ns, t0 + t, lane, act);
+            const int src = tile_source(&s_slot[wave_base], ns, t0 + t, lane, act);
             float feat[8];
-            tile_encode<TAB16>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
+            tile_encode<TAB16, false>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
             xin[t] = H::pack(feat);
             shh[t] = s_sh[(wave_base + src) * 4 + (lane >> 4)];
           }
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(kBlock, 4) void render_kernel(RenderArgs A) {
     if (has) {
       const float sd = expf(so0) * F.dt;
       const float trans = expf(-sd);
-      const float wgt = T * (-expm1f(-sd));
+      const float wgt = T * (1.0f - trans);
       cr = fmaf(wgt, sigmoidf(sl0), cr);
       cg = fmaf(wgt, sigmoidf(sl1), cg);
       cb = fmaf(wgt, sigmoidf(sl2), cb);
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void encode_kernel(FieldDev F, const float*
   }
   float f[8];
   uint32_t fetches = 0;
-  encode_point<TAB16>(F, s_lv, table_rsrc(F), x, lstar, act, g, f, fetches);
+  encode_point<TAB16, true>(F, s_lv, table_rsrc(F), x, lstar, act, g, f, fetches);
   if (!act) return;
   for (int j = 0; j < 4; ++j) {
     const int lev = g + 4 * j;

@@ -1,0 +1,97 @@
+"""Precision path (FP16 hash tables, FP16 / BF16 MLP on MFMA with FP32
+accumulation, FP32 march and compositing): per-image error against the FP64
+oracle and against the FP32 GPU path, on the 3.2 m config-1 field at a
+2048x2048 eye buffer along the seeded walk.  The FP16 path must meet the
+budget fixed in advance -- mean abs <= 1/4095 and max abs <= 1/1023 PQ (one
+10-bit PQ code) -- BF16 is reported with its error."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import need_gpu
+from oracle.render import all_pixels, render_fp64
+from paper_2311_02542_amd import capi, synth
+
+pytestmark = pytest.mark.gpu
+BUDGET_MEAN, BUDGET_MAX = 1 / 4095, 1 / 1023
+
+
+@pytest.fixture(scope="module")
+def R():
+    need_gpu()
+    r = capi.Renderer(0)
+    yield r
+    r.close()
+
+
+def _err(a, b):
+    e = np.abs(np.asarray(a, np.float64)[..., :3] - np.asarray(b, np.float64)[..., :3])
+    mse = float(np.mean(e ** 2))
+    return float(e.max()), float(e.mean()), 10 * math.log10(1 / max(mse, 1e-30))
+
+
+def test_c3_precision_report(R):
+    torch = R.torch
+    f32 = synth.field_c3(table_dtype=np.float32)     # the field before FP16 rounding
+    f16 = synth.field_c3()                           # FP16 tables (the config's form)
+    cams = synth.cameras_c3(32)
+    W = H = 2048
+    fid32, fid16 = R.load(f32), R.load(f16)
+    poses = [0, 11, 31]
+    crop = 48
+    r0 = (H - crop) // 2
+    px = all_pixels(1, W, H, rows=np.arange(r0, r0 + crop), cols=np.arange(r0, r0 + crop))
+    report = {}
+    for pi in poses:
+        cam = [cams[pi]]
+        ref = render_fp64(f32, cam, W, H, pixels=px)
+        ref16 = render_fp64(f16, cam, W, H, pixels=px)   # isolates arithmetic from table rounding
+        gpu32, _ = R.render(fid32, cam, W, H, "f32")
+        outs = {}
+        for path in ("f16", "bf16"):
+            outs[path], _ = R.render(fid16, cam, W, H, path)
+        torch.cuda.synchronize()
+        g32 = gpu32.cpu().numpy()[0]
+        sel = lambda img: img[r0:r0 + crop, r0:r0 + crop].reshape(-1, 4)
+        report.setdefault("f32_vs_oracle", []).append(_err(sel(g32), ref["rgba"]))
+        for path, img in outs.items():
+            im = img.cpu().numpy()[0]
+            report.setdefault(f"{path}_vs_oracle", []).append(_err(sel(im), ref["rgba"]))
+            report.setdefault(f"{path}_vs_oracle_fp16_tables", []).append(_err(sel(im), ref16["rgba"]))
+            report.setdefault(f"{path}_vs_gpu_fp32_full_image", []).append(_err(im, g32))
+    R.unload(fid32)
+    R.unload(fid16)
+    for k, v in report.items():
+        mx = max(x[0] for x in v)
+        mean = float(np.mean([x[1] for x in v]))
+        psnr = min(x[2] for x in v)
+        print(f"{k:34s} max {mx:.3e} mean {mean:.3e} PSNR_PQ {psnr:.1f} dB")
+    f16_max = max(x[0] for x in report["f16_vs_oracle"])
+    f16_mean = float(np.mean([x[1] for x in report["f16_vs_oracle"]]))
+    assert f16_max <= BUDGET_MAX and f16_mean <= BUDGET_MEAN
+    assert max(x[0] for x in report["f32_vs_oracle"]) <= 1e-5
+    # BF16 carries 8 mantissa bits: reported, only sanity-bounded here
+    assert max(x[0] for x in report["bf16_vs_oracle"]) < 0.05
+
+
+def test_c4_precision_sampled(R):
+    torch = R.torch
+    f32 = synth.field_c4(table_dtype=np.float32)
+    f16 = dict(f32)
+    f16["tables"] = f32["tables"].astype(np.float16)
+    cams = synth.cameras_c4([150])[0]
+    fid = R.load(f16)
+    rng = np.random.default_rng(9)
+    m = 600
+    px = np.stack([rng.integers(0, 2, m), rng.integers(0, 2048, m), rng.integers(0, 2048, m)], 1)
+    ref = render_fp64(f32, cams, 2048, 2048, pixels=px)
+    sel = (px[:, 0] * 2048 + px[:, 1]) * 2048 + px[:, 2]
+    res = {}
+    for path in ("f16", "bf16"):
+        img, _ = R.render(fid, cams, 2048, 2048, path)
+        torch.cuda.synchronize()
+        res[path] = _err(img.cpu().numpy().reshape(-1, 4)[sel], ref["rgba"])
+        print(f"c4 {path}: max {res[path][0]:.3e} mean {res[path][1]:.3e} PSNR_PQ {res[path][2]:.1f} dB")
+    R.unload(fid)
+    assert res["f16"][0] <= BUDGET_MAX and res["f16"][1] <= BUDGET_MEAN
