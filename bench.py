@@ -25,9 +25,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "render_kernel_c4_stereo.md")
 MFMA_PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "f32": 157.3}
 # MLP FLOPs per evaluated sample (unpadded): density 32x64 + 64x16, color 31x64 + 64x64 + 64x3
 MLP_FLOPS_C4 = 2 * (32 * 64 + 64 * 16 + 31 * 64 + 64 * 64 + 64 * 3)
+
+
+def source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2311_02542_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(src, "*.hip")) + glob.glob(os.path.join(src, "*.hpp"))
+                    + glob.glob(os.path.join(src, "*.cpp"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(path):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return None
+    if f"source sha256: {source_hash()}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith(f"traffic_bytes_per_launch {path}:"):
+            return float(line.split(":")[1])
+    return None
 
 
 def parse():
@@ -136,6 +164,7 @@ def main():
     fids = {}
     results = {}
     for p in paths:
+        print(f"bench: timing path {p}", file=sys.stderr, flush=True)
         fld = field16 if p in ("f16", "bf16") else field32
         fids[p] = R.load(fld)
         r = time_path(R, fids[p], frames, W, H, p, args.steps, args.warmup)
@@ -160,6 +189,7 @@ def main():
         del r
     err = {}
     if not args.no_error:
+        print("bench: PQ error vs oracle", file=sys.stderr, flush=True)
         for p in paths:
             err[p] = pq_error(R, fids[p], field32, frames[0], W, H, p, args.error_pixels)
     head = "f16" if "f16" in results else paths[0]
@@ -184,7 +214,7 @@ def main():
         "paths": results, "pq_error": err, "error_budget": {"mean_abs": 1 / 4095, "max_abs": 1 / 1023,
                                                              "head_path_meets": budget_ok},
         "roofline": {"bound": "hbm", "achieved": hr["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": hr["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": hr["achieved_GBs"] / HBM_PEAK_GBS, "traffic": profiled_traffic(head),
                      "kernel": "render_kernel", "algorithmic_bytes_per_launch": hr["bytes_per_launch"]},
         "mfma": {"achieved_TFLOPs": hr["mfma_TFLOPs"], "peak_TFLOPs": MFMA_PEAK_TFLOPS[head],
                  "frac": hr["mfma_TFLOPs"] / MFMA_PEAK_TFLOPS[head]},
@@ -199,6 +229,7 @@ def main():
         line["calib_copy_bytes"] = src.numel() * 4
         del src, dst
     if not args.no_cpu_baseline:
+        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(field32, frames[0], W, H, args.cpu_crop)
     R.close()
     print(json.dumps(line), flush=True)

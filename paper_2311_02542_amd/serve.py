@@ -28,6 +28,7 @@ import argparse
 import collections
 import json
 import math
+import sys
 import threading
 import time
 
@@ -237,11 +238,14 @@ class Server:
                 return None
             head = self.pending.popleft()
             batch = [head]
-            if len(head.cams) == 1 and self.max_batch > 1:
+            # merged cameras must fit the budget beside the fixed allocations
+            fit = (self.budget - self.fixed_bytes) // max(1, head.W * head.H * 20)
+            limit = min(self.max_batch, max(1, int(fit)))
+            if len(head.cams) == 1 and limit > 1:
                 keep = collections.deque()
                 while self.pending:
                     r = self.pending.popleft()
-                    if (len(batch) < self.max_batch and len(r.cams) == 1 and r.scene == head.scene
+                    if (len(batch) < limit and len(r.cams) == 1 and r.scene == head.scene
                             and r.W == head.W and r.H == head.H):
                         batch.append(r)
                     else:
@@ -264,6 +268,18 @@ class Server:
                 if batch is not None:
                     if self._launch(free[0], batch):
                         launched = True
+                    elif len(free) == len(self.slots):
+                        # nothing in flight will free memory: shrink to the head
+                        # request, and fail it if even that cannot be admitted
+                        head, rest = batch[0], batch[1:]
+                        self._requeue(rest)
+                        if not self._launch(free[0], [head]):
+                            head.error = ServeError("request does not fit the HBM budget")
+                            head.done.set()
+                            with self.lock:
+                                self.done_list.append(head)
+                        else:
+                            launched = True
                     else:
                         self._requeue(batch)
             if not launched:
@@ -326,6 +342,7 @@ def main():
     for q in spec:
         cams, W, H = synth.request_cameras(q["scene"], q["kind"], q["pose_seed"])
         work.append((q["scene"], cams, W, H))
+    print("serve: serial f32 baseline", file=sys.stderr, flush=True)
     base.run_serial(work[:10])
     t0 = time.perf_counter()
     lat = np.array(base.run_serial(work))
@@ -337,11 +354,13 @@ def main():
     base.close()
     srv = Server(fields, budget, n_slots=args.slots, compute="f16", use_graphs=True)
     # capacity of the serving path: a saturating burst
+    print("serve: saturating burst", file=sys.stderr, flush=True)
     reqs, wall = drive(srv, args.requests, 1e6)
     cap = len(reqs) / wall
     out["burst"] = summarize(reqs, wall)
     out["burst"]["req_per_s"] = cap
     for load in [float(x) for x in args.loads.split(",")]:
+        print(f"serve: load {load}", file=sys.stderr, flush=True)
         reqs, wall = drive(srv, args.requests, load * cap, seed=6000 + int(load * 100))
         out[f"load_{load:g}"] = summarize(reqs, wall)
         out[f"load_{load:g}"]["rate_hz"] = load * cap

@@ -40,20 +40,25 @@ def test_c3_precision_report(R):
     fid32, fid16 = R.load(f32), R.load(f16)
     poses = [0, 11, 31]
     crop = 48
-    r0 = (H - crop) // 2
-    px = all_pixels(1, W, H, rows=np.arange(r0, r0 + crop), cols=np.arange(r0, r0 + crop))
     report = {}
     for pi in poses:
         cam = [cams[pi]]
-        ref = render_fp64(f32, cam, W, H, pixels=px)
-        ref16 = render_fp64(f16, cam, W, H, pixels=px)   # isolates arithmetic from table rounding
         gpu32, _ = R.render(fid32, cam, W, H, "f32")
         outs = {}
         for path in ("f16", "bf16"):
             outs[path], _ = R.render(fid16, cam, W, H, path)
         torch.cuda.synchronize()
         g32 = gpu32.cpu().numpy()[0]
-        sel = lambda img: img[r0:r0 + crop, r0:r0 + crop].reshape(-1, 4)
+        # oracle crop: the crop x crop window with the most content (alpha)
+        a = g32[..., 3].astype(np.float64)
+        box = np.cumsum(np.cumsum(np.pad(a, ((1, 0), (1, 0))), 0), 1)
+        win = box[crop:, crop:] - box[:-crop, crop:] - box[crop:, :-crop] + box[:-crop, :-crop]
+        r0, c0 = np.unravel_index(np.argmax(win), win.shape)
+        print(f"pose {pi}: content {np.mean(a > 0):.3f} of pixels, crop at ({r0}, {c0}) alpha {win[r0, c0] / crop ** 2:.3f}")
+        px = all_pixels(1, W, H, rows=np.arange(r0, r0 + crop), cols=np.arange(c0, c0 + crop))
+        ref = render_fp64(f32, cam, W, H, pixels=px)
+        ref16 = render_fp64(f16, cam, W, H, pixels=px)   # isolates arithmetic from table rounding
+        sel = lambda img: img[r0:r0 + crop, c0:c0 + crop].reshape(-1, 4)
         report.setdefault("f32_vs_oracle", []).append(_err(sel(g32), ref["rgba"]))
         for path, img in outs.items():
             im = img.cpu().numpy()[0]
