@@ -96,12 +96,20 @@ typedef struct {
   uint32_t row_begin, row_end;
 } vrn_camera;
 
+typedef enum {
+  VRN_OUT_PQ = 0,             /* PQ RGB as composited (Sec. 4.1) */
+  VRN_OUT_LINEAR = 1,         /* linear HDR: 100 * PQ^-1 per channel (linear 1 = 100 cd/m^2) */
+  VRN_OUT_SRGB = 2            /* display: sRGB transfer of clip(2^exposure_ev * linear, 0, 1)
+                                 (render-time exposure, Fig. exposure-swipe) */
+} vrn_output;
+
 typedef struct {
   vrn_dtype compute;          /* MLP arithmetic: VRN_F32 (FP32 MFMA), VRN_F16 or
                                  VRN_BF16 (MFMA, FP32 accumulate); march,
                                  transmittance and compositing are FP32 always */
-  int32_t output_linear_hdr;  /* 0: PQ RGB; 1: linear HDR (100 * PQ^-1 per channel) */
+  int32_t output;             /* vrn_output; alpha is 1 - T in every mode */
   uint32_t march_budget;      /* lattice steps per march round, 0 = default */
+  float exposure_ev;          /* exposure in stops for VRN_OUT_SRGB */
 } vrn_render_opts;
 
 /* Work counters accumulated in a workspace by every render. */
@@ -203,6 +211,27 @@ vrn_status vrn_encode(vrn_ctx* ctx, vrn_field_id field, const float* d_xyz, cons
  * (exp of density output 0), d_rgb [n][3] (sigmoid, PQ units). */
 vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const float* d_dir,
                    uint32_t n, vrn_dtype compute, float* d_sigma, float* d_rgb, void* hip_stream);
+
+/* ---- occupancy maintenance ---- */
+
+/* Grid-based occupancy pruning (Sec. 4.3 "Joint history- and grid-based
+ * pruning"; App. C: 4 evenly placed points per voxel).  For every occupied
+ * voxel of the resident field, the density MLP (all hash levels, no LOD) is
+ * evaluated at points_per_voxel points -- 4: the alternating corners of the
+ * voxel's 2x2x2 sub-lattice at offsets {1/4, 3/4}; 1, 8, 27, 64: a p^3 grid
+ * at (i + 1/2) / p -- and the voxel is kept iff the worst-case opacity
+ * 1 - exp(-sigma_max dt) >= alpha.  Pruning only clears bits.
+ *   d_bits_out     device, ceil(G^3 / 32) uint32 words, bit i = x + G*(y + G*z).
+ *   d_max_opacity  device [G^3] float (NaN for unoccupied voxels) or NULL.
+ * The resident field is not modified (see vrn_set_occupancy). */
+vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_t points_per_voxel,
+                          vrn_dtype compute, uint32_t* d_bits_out, float* d_max_opacity, void* hip_stream);
+
+/* Replace a resident field's occupancy with device bits (same layout as
+ * vrn_field_desc.occ_bits), rebuilding its bricks and coarse grid on
+ * hip_stream.  Renders of this field on other streams must be ordered by
+ * the caller. */
+vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -32,8 +32,9 @@ def thresholds(t_min, band):
 
 
 def step(st, rows, sigma, rgb, dt, t_min, band, levels=None):
-    """Composite one sample for each ray index in ``rows`` (in order)."""
-    alpha = 1.0 - np.exp(-np.asarray(sigma, np.float64) * np.float64(np.float32(dt)))
+    """Composite one sample for each ray index in ``rows`` (in order); dt is
+    the step length (a scalar, or one per sample)."""
+    alpha = 1.0 - np.exp(-np.asarray(sigma, np.float64) * np.asarray(dt, np.float32).astype(np.float64))
     T = st["T"][rows]
     st["C"][rows] += (T * alpha)[:, None] * rgb
     st["T"][rows] = T * (1.0 - alpha)

@@ -20,6 +20,8 @@ only to pin the march: its cell intervals must contain the same samples.
 """
 import numpy as np
 
+from .geometry import contract32, is_contracted, lattice_table, pipeline_field
+
 F32 = np.float32
 
 
@@ -95,6 +97,39 @@ def occupied(c, valid, field):
     return valid & (((word >> (idx & 31).astype(np.uint32)) & 1) == 1)
 
 
+def uses_table(field):
+    return is_contracted(field) or float(field.get("step_growth", 0.0)) > 0.0
+
+
+def sample_points(field, o, d, k):
+    """Canonical FP32 sample points for o, d [n, 3] and lattice indices k
+    [n, K]: returns (y, t) with y in the coordinates the occupancy and hash
+    grids use (world for bounded fields, contracted for unbounded ones)."""
+    if not uses_table(field):
+        return canonical_positions(o, d, k, field["dt"])
+    tab, _ = lattice_table(field)
+    tk = tab[np.clip(k, 0, tab.size - 1)]
+    o = np.asarray(o, F32)
+    d = np.asarray(d, F32)
+    x = np.stack([o[:, a:a + 1] + tk * d[:, a:a + 1] for a in range(3)], axis=-1)
+    return (contract32(x, field) if is_contracted(field) else x), tk
+
+
+def sample_range(field, o, d):
+    """Inclusive lattice index range [k_lo, k_hi] worth testing per ray."""
+    if is_contracted(field):
+        n = o.shape[0]
+        return np.zeros(n, np.int64), np.full(n, int(field["max_lattice"]) - 1, np.int64)
+    t_near, t_far = slab_fp64(o, d, field["aabb_min"], field["extent"])
+    if not uses_table(field):
+        return lattice_range(t_near, t_far, field["dt"])
+    tab, _ = lattice_table(field)
+    hit = t_far >= np.maximum(t_near, 0.0)
+    lo = np.maximum(np.searchsorted(tab, np.where(np.isfinite(t_near), t_near, 0.0)) - 2, 0)
+    hi = np.minimum(np.searchsorted(tab, np.where(np.isfinite(t_far), t_far, 0.0)) + 1, tab.size - 1)
+    return lo.astype(np.int64), np.where(hit, hi, -1).astype(np.int64)
+
+
 def dense_masked_march(field, o, d, chunk=512):
     """Evaluated lattice indices per ray, in increasing k, capped.
 
@@ -102,8 +137,8 @@ def dense_masked_march(field, o, d, chunk=512):
     o = np.asarray(o, F32)
     d = np.asarray(d, F32)
     n = o.shape[0]
-    t_near, t_far = slab_fp64(o, d, field["aabb_min"], field["extent"])
-    k_lo, k_hi = lattice_range(t_near, t_far, field["dt"])
+    k_lo, k_hi = sample_range(field, o, d)
+    pf = pipeline_field(field)
     cap = int(field["max_samples"])
     span = int(np.max(k_hi - k_lo + 1, initial=0))
     rows, cols = [], []
@@ -114,9 +149,9 @@ def dense_masked_march(field, o, d, chunk=512):
         inr = (k <= k_hi[:, None]) & (counts[:, None] < cap)
         if not inr.any():
             break
-        x, _ = canonical_positions(o, d, k, field["dt"])
-        _, c, valid = canonical_cells(x, field)
-        ev = occupied(c, valid & inr, field)
+        y, _ = sample_points(field, o, d, k)
+        _, c, valid = canonical_cells(y, pf)
+        ev = occupied(c, valid & inr, pf)
         # cap: keep at most cap - counts samples per ray from this chunk
         rank = np.cumsum(ev, axis=1) + counts[:, None]
         ev &= rank <= cap

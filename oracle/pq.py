@@ -38,3 +38,17 @@ def linear_to_pq(lin):
 def pq_to_linear(e):
     """PQ units back to linear HDR color (Sec. 4.1 scale)."""
     return pq_decode(e) * (PEAK_NITS / NITS_PER_LINEAR_UNIT)
+
+
+def srgb_oetf(v):
+    """sRGB transfer function (IEC 61966-2-1) on linear values in [0, 1]."""
+    v = np.clip(np.asarray(v, np.float64), 0.0, 1.0)
+    return np.where(v <= 0.0031308, 12.92 * v, 1.055 * np.power(v, 1.0 / 2.4) - 0.055)
+
+
+def pq_to_display(e, exposure_ev=0.0):
+    """Display tonemap of a PQ color (Sec. 4.1, Fig. exposure-swipe): decode to
+    linear HDR, scale by 2^EV, clip to [0, 1], apply the sRGB transfer.
+    Reading: the paper sweeps exposure at render time without giving its
+    tonemapper; a clipped exposure scale with the sRGB curve is the plain one."""
+    return srgb_oetf(pq_to_linear(e) * (2.0 ** exposure_ev))

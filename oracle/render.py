@@ -13,10 +13,11 @@ import numpy as np
 
 from . import composite as comp
 from .encoding import encode, level_star, lod_weights
-from .march import canonical_positions, dense_masked_march
+from .geometry import contract64, is_contracted, lattice_table, pipeline_field
+from .march import dense_masked_march, sample_points, uses_table
 from .mlp import color_mlp, density_mlp
 from .pq import pq_to_linear
-from .rays import canonical_rays, cone_pitch
+from .rays import canonical_rays, cone_pitch, fp64_directions
 from .sh import sh_basis
 
 
@@ -27,11 +28,30 @@ def all_pixels(n_cams, W, H, rows=None, cols=None):
     return np.stack([c.ravel(), r.ravel(), x.ravel()], axis=1)
 
 
+def contracted_level_star(field, cam, cols, rows, o, t):
+    """L* from the footprint between corresponding sample points of adjacent
+    rays in contracted space (Sec. 4.2.1), FP64, normalised by the cube edge 4."""
+    d0 = fp64_directions(cam, cols, rows)
+    d1 = fp64_directions(cam, np.asarray(cols) + 1, rows)
+    o64 = np.asarray(o, np.float64)
+    t = np.asarray(t, np.float64)[:, None]
+    y0 = contract64(o64 + t * d0, field)
+    y1 = contract64(o64 + t * d1, field)
+    rhat = float(field.get("lod_radius_scale", 1.0)) * np.linalg.norm(y1 - y0, axis=-1) / 4.0
+    s = np.float64(np.float32(field["base_res"]))
+    f = np.float64(np.float32(field["growth"]))
+    ls = -np.log(2.0 * s * rhat) / np.log(f) + np.float64(np.float32(field["lod_bias"]))
+    return np.maximum(ls, 0.0)
+
+
 def _render_batch(field, cam, rows, cols, band, rank_block, keep_k):
     o, d = canonical_rays(cam, cols, rows)
     n = o.shape[0]
     lod = bool(field["lod_enable"])
-    r = cone_pitch(cam, cols, rows, float(field["lod_radius_scale"])) if lod else None
+    contracted = is_contracted(field)
+    pf = pipeline_field(field)
+    deltas = lattice_table(field)[1] if uses_table(field) else None
+    r = cone_pitch(cam, cols, rows, float(field["lod_radius_scale"])) if lod and not contracted else None
     ks, counts = dense_masked_march(field, o, d)
     sh = sh_basis(d.astype(np.float64), int(field["sh_bands"]))
     st = comp.new_state(n)
@@ -46,13 +66,16 @@ def _render_batch(field, cam, rows, cols, band, rank_block, keep_k):
         ok = jj < counts[rr]
         rr, jj = rr[ok], jj[ok]
         k = ks[rr, jj]
-        x, tk = canonical_positions(o[rr], d[rr], k[:, None], field["dt"])
+        x, tk = sample_points(field, o[rr], d[rr], k[:, None])
         x, tk = x[:, 0, :], tk[:, 0]
-        if lod:
+        if lod and contracted:
+            w = lod_weights(contracted_level_star(field, cam, cols[rr], rows[rr], o[rr], tk), L)
+        elif lod:
             w = lod_weights(level_star(tk.astype(np.float64), r[rr], field), L)
         else:
             w = np.ones((rr.size, L))
-        feats = encode(field, x, w)
+        step_len = deltas[k] if deltas is not None else np.full(k.size, np.float32(field["dt"]))
+        feats = encode(pf, x, w)
         sigma, geo = density_mlp(feats, field["mlp"])
         rgb = color_mlp(geo, sh[rr], field["mlp"])
         nlev = (w > 0).sum(axis=1)
@@ -63,7 +86,7 @@ def _render_batch(field, cam, rows, cols, band, rank_block, keep_k):
             if not keep.any():
                 continue
             idx = np.nonzero(sel)[0][keep]
-            comp.step(st, rr[idx], sigma[idx], rgb[idx], field["dt"], float(field["t_min"]),
+            comp.step(st, rr[idx], sigma[idx], rgb[idx], step_len[idx], float(field["t_min"]),
                       band, nlev[idx])
     comp.finish(st)
     out = {

@@ -50,7 +50,11 @@ class VrnCamera(ctypes.Structure):
 
 
 class VrnRenderOpts(ctypes.Structure):
-    _fields_ = [("compute", c_i32), ("output_linear_hdr", c_i32), ("march_budget", c_u32)]
+    _fields_ = [("compute", c_i32), ("output", c_i32), ("march_budget", c_u32), ("exposure_ev", c_f)]
+
+
+VRN_OUT_PQ, VRN_OUT_LINEAR, VRN_OUT_SRGB = 0, 1, 2
+OUTPUTS = {"pq": VRN_OUT_PQ, "linear": VRN_OUT_LINEAR, "srgb": VRN_OUT_SRGB}
 
 
 class VrnStats(ctypes.Structure):
@@ -97,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                               c_vp]),
         "vrn_encode": (c_i32, [c_vp, c_u32, c_vp, c_vp, c_vp, c_u32, c_vp, c_vp]),
         "vrn_mlp": (c_i32, [c_vp, c_u32, c_vp, c_vp, c_u32, c_i32, c_vp, c_vp, c_vp]),
+        "vrn_prune_grid": (c_i32, [c_vp, c_u32, c_f, c_u32, c_i32, c_vp, c_vp, c_vp]),
+        "vrn_set_occupancy": (c_i32, [c_vp, c_u32, c_vp, c_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -242,21 +248,25 @@ def vrn_workspace_init(ctx, workspace, stream=None):
                                   _stream(stream)), lib)
 
 
-def render_opts(compute="f32", linear_hdr=False, march_budget=0):
+def render_opts(compute="f32", linear_hdr=False, march_budget=0, output=None, exposure_ev=0.0):
+    """output: "pq" (default), "linear" or "srgb"; linear_hdr=True is "linear"."""
     o = VrnRenderOpts()
     o.compute = DTYPES[compute] if isinstance(compute, str) else int(compute)
-    o.output_linear_hdr = int(bool(linear_hdr))
+    if output is None:
+        output = "linear" if linear_hdr else "pq"
+    o.output = OUTPUTS[output] if isinstance(output, str) else int(output)
     o.march_budget = int(march_budget)
+    o.exposure_ev = float(exposure_ev)
     return o
 
 
 def vrn_render(ctx, fid, cams, W, H, rgba, nsamples=None, compute="f32", linear_hdr=False,
-               workspace=None, stream=None, march_budget=0):
+               workspace=None, stream=None, march_budget=0, output=None, exposure_ev=0.0):
     """Enqueue a render of host cameras into the device tensors rgba
     [n_cams, H, W, 4] float32 and nsamples [n_cams, H, W] int32 (optional)."""
     lib = load_library()
     arr = make_cameras(cams, H)
-    opts = render_opts(compute, linear_hdr, march_budget)
+    opts = render_opts(compute, linear_hdr, march_budget, output, exposure_ev)
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(lib.vrn_render(ctx, fid, arr, len(cams), W, H, ctypes.byref(opts), _ptr(rgba),
                           _ptr(nsamples), _ptr(workspace), ws_bytes, _stream(stream)), lib)
@@ -313,6 +323,19 @@ def vrn_mlp(ctx, fid, feat, dirs, n, compute, sigma, rgb, stream=None):
                        _stream(stream)), lib)
 
 
+def vrn_prune_grid(ctx, fid, alpha, bits_out, max_opacity=None, points_per_voxel=4, compute="f32",
+                   stream=None):
+    lib = load_library()
+    c = DTYPES[compute] if isinstance(compute, str) else int(compute)
+    _check(lib.vrn_prune_grid(ctx, fid, float(alpha), int(points_per_voxel), c, _ptr(bits_out),
+                              _ptr(max_opacity), _stream(stream)), lib)
+
+
+def vrn_set_occupancy(ctx, fid, bits, stream=None):
+    lib = load_library()
+    _check(lib.vrn_set_occupancy(ctx, fid, _ptr(bits), _stream(stream)), lib)
+
+
 # ---------------------------------------------------------------------------
 # convenience
 # ---------------------------------------------------------------------------
@@ -335,7 +358,7 @@ class Renderer:
         vrn_unload_field(self.ctx, fid)
 
     def render(self, fid, cams, W, H, compute="f32", linear_hdr=False, out=None, stream=None,
-               march_budget=0):
+               march_budget=0, output=None, exposure_ev=0.0):
         torch = self.torch
         n = len(cams)
         if out is None:
@@ -344,7 +367,7 @@ class Renderer:
         else:
             rgba, ns = out
         vrn_render(self.ctx, fid, cams, W, H, rgba, ns, compute, linear_hdr, self.ws, stream,
-                   march_budget)
+                   march_budget, output, exposure_ev)
         return rgba, ns
 
     def stats(self):

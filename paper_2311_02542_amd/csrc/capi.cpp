@@ -236,6 +236,10 @@ void track(Field* f, hipStream_t s) {
 vrn_status check_opts(const vrn_render_opts* opts) {
   if (opts && opts->compute != VRN_F32 && opts->compute != VRN_F16 && opts->compute != VRN_BF16)
     return fail(VRN_ERR_INVALID_ARG, "opts.compute must be VRN_F32, VRN_F16 or VRN_BF16");
+  if (opts && (opts->output < VRN_OUT_PQ || opts->output > VRN_OUT_SRGB))
+    return fail(VRN_ERR_INVALID_ARG, "opts.output must be VRN_OUT_PQ, VRN_OUT_LINEAR or VRN_OUT_SRGB");
+  if (opts && (!finite(opts->exposure_ev) || std::fabs(opts->exposure_ev) > 64.0f))
+    return fail(VRN_ERR_INVALID_ARG, "opts.exposure_ev must be finite, |ev| <= 64");
   return VRN_OK;
 }
 
@@ -251,7 +255,8 @@ vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t 
   a.rgba = d_rgba;
   a.nsamples = d_nsamples;
   a.ws = static_cast<uint8_t*>(ws);
-  a.linear_hdr = opts ? opts->output_linear_hdr : 0;
+  a.output = opts ? opts->output : VRN_OUT_PQ;
+  a.exposure = opts ? std::exp2(opts->exposure_ev) : 1.0f;
   a.budget = (opts && opts->march_budget) ? opts->march_budget : 256u;
   const int compute = opts ? (int)opts->compute : 0;
   const uint64_t rays = (uint64_t)n_cams * W * H;
@@ -605,6 +610,39 @@ vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const 
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = launch_mlp(f->dev, d_feat, d_dir, n, (int)compute, d_sigma, d_rgb, s);
   if (e != hipSuccess) return hip_fail(e, "mlp");
+  track(f, s);
+  return VRN_OK;
+}
+
+vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_t points_per_voxel,
+                          vrn_dtype compute, uint32_t* d_bits_out, float* d_max_opacity, void* stream) {
+  if (!ctx || !d_bits_out) return fail(VRN_ERR_INVALID_ARG, "ctx or d_bits_out is NULL");
+  if (!finite(alpha) || alpha < 0.0f || alpha > 1.0f) return fail(VRN_ERR_INVALID_ARG, "alpha must be in [0, 1]");
+  if (points_per_voxel != 4 && points_per_voxel != 1 && points_per_voxel != 8 && points_per_voxel != 27 &&
+      points_per_voxel != 64)
+    return fail(VRN_ERR_UNSUPPORTED, "points_per_voxel must be 4 or a cube 1, 8, 27, 64");
+  if (compute != VRN_F32 && compute != VRN_F16 && compute != VRN_BF16)
+    return fail(VRN_ERR_INVALID_ARG, "compute must be VRN_F32, VRN_F16 or VRN_BF16");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_prune(f->dev, alpha, points_per_voxel, (int)compute, d_bits_out, d_max_opacity, s);
+  if (e != hipSuccess) return hip_fail(e, "prune");
+  track(f, s);
+  return VRN_OK;
+}
+
+vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* stream) {
+  if (!ctx || !d_bits) return fail(VRN_ERR_INVALID_ARG, "ctx or d_bits is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_set_occupancy(f->dev, d_bits, s);
+  if (e != hipSuccess) return hip_fail(e, "set occupancy");
   track(f, s);
   return VRN_OK;
 }

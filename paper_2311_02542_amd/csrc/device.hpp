@@ -72,15 +72,18 @@ __device__ __forceinline__ void canonical_ray(const vrn_camera& c, uint32_t col,
 // pixel and its right neighbour, 2 sin(theta / 2), evaluated without
 // cancellation: sin(theta) = |w x v| / (|w| |w + v|) with v = R[:,0] / fx.
 __device__ __forceinline__ float cone_pitch(const vrn_camera& c, const float w[3], float n, float scale) {
-  const float v[3] = {c.c2w[0] / c.fx, c.c2w[4] / c.fx, c.c2w[8] / c.fx};
+  // continuous quantity (it only places the LOD weights): hardware
+  // reciprocal / square root are accurate to ~1 ulp, far below what matters
+  const float ifx = __builtin_amdgcn_rcpf(c.fx);
+  const float v[3] = {c.c2w[0] * ifx, c.c2w[4] * ifx, c.c2w[8] * ifx};
   const float e[3] = {w[0] + v[0], w[1] + v[1], w[2] + v[2]};
   const float cx = w[1] * v[2] - w[2] * v[1];
   const float cy = w[2] * v[0] - w[0] * v[2];
   const float cz = w[0] * v[1] - w[1] * v[0];
-  const float ne = sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-  const float sn = sqrtf(cx * cx + cy * cy + cz * cz) / (n * ne);
-  const float cs = (w[0] * e[0] + w[1] * e[1] + w[2] * e[2]) / (n * ne);
-  return scale * sn / sqrtf(0.5f * (1.0f + cs));
+  const float inv = __builtin_amdgcn_rcpf(n * __builtin_amdgcn_sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
+  const float sn = __builtin_amdgcn_sqrtf(cx * cx + cy * cy + cz * cz) * inv;
+  const float cs = (w[0] * e[0] + w[1] * e[1] + w[2] * e[2]) * inv;
+  return scale * sn * __builtin_amdgcn_rsqf(0.5f * (1.0f + cs));
 }
 
 // Lattice range [k_lo, k_hi] from an FP32 slab test padded by two steps on
@@ -127,7 +130,7 @@ __device__ __forceinline__ void setup_ray(const FieldDev& F, const vrn_camera& c
   r.dx = d[0];
   r.dy = d[1];
   r.dz = d[2];
-  r.lr = F.lod ? logf(cone_pitch(c, w, n, F.lod_radius_scale)) + F.lod_c : 0.0f;
+  r.lr = F.lod ? __logf(cone_pitch(c, w, n, F.lod_radius_scale)) + F.lod_c : 0.0f;
   r.brick = -1;
   r.blo = r.bhi = 0u;
   lattice_range(F, r);
@@ -210,11 +213,16 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
     float t, x[3], q[3];
     lattice_q(F, r, r.k, t, x, q);
     const int cx = cell_of(q[0], G), cy = cell_of(q[1], G), cz = cell_of(q[2], G);
-    bool moved = false;
+    // empty box to try to jump over: origin (in units of its size) and size
+    int bo[3] = {0, 0, 0};
+    float bsize = 0.0f;
     if ((unsigned)cx < (unsigned)G && (unsigned)cy < (unsigned)G && (unsigned)cz < (unsigned)G) {
       const int bx = cx >> F.cshift, by = cy >> F.cshift, bz = cz >> F.cshift;
       if (!bit_set(coarse, (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz))) {
-        moved = skip_box(F, r, q, bx, by, bz, cb);
+        bo[0] = bx;
+        bo[1] = by;
+        bo[2] = bz;
+        bsize = cb;
       } else {
         const int kx = cx >> 2, ky = cy >> 2, kz = cz >> 2;
         const int brick = kx + (int)F.Gb * (ky + (int)F.Gb * kz);
@@ -225,7 +233,10 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
           r.bhi = (uint32_t)(b >> 32);
         }
         if ((r.blo | r.bhi) == 0u) {
-          moved = skip_box(F, r, q, kx, ky, kz, 4.0f);
+          bo[0] = kx;
+          bo[1] = ky;
+          bo[2] = kz;
+          bsize = 4.0f;
         } else {
           const uint32_t bit = (uint32_t)((cx & 3) + 4 * (cy & 3) + 16 * (cz & 3));
           const uint32_t word = bit < 32u ? r.blo : r.bhi;
@@ -240,6 +251,7 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
         }
       }
     }
+    const bool moved = bsize > 0.0f && skip_box(F, r, q, bo[0], bo[1], bo[2], bsize);
     if (!moved) r.k++;
   }
   return 0;
@@ -394,7 +406,7 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
 // Optimal LOD level L* = -log_f(2 s r_hat) + bias, clamped at 0 (Sec. 4.2.1-2),
 // with r_hat = t r / extent and lr = ln(r) + ln(2 s / extent).
 __device__ __forceinline__ float level_star(const FieldDev& F, float t, float lr) {
-  return fmaxf(-(logf(t) + lr) * F.inv_ln_f + F.lod_bias, 0.0f);
+  return fmaxf(-(__logf(t) + lr) * F.inv_ln_f + F.lod_bias, 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -766,6 +778,12 @@ __device__ __forceinline__ float pq_to_linear(float e) {
   const float ep = powf(fmaxf(e, 0.0f), 1.0f / m2);
   const float y = powf(fmaxf(ep - c1, 0.0f) / (c2 - c3 * ep), 1.0f / m1);
   return 100.0f * y;
+}
+
+// sRGB transfer (IEC 61966-2-1) of a linear value clipped to [0, 1].
+__device__ __forceinline__ float srgb_oetf(float v) {
+  v = __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f);
+  return v <= 0.0031308f ? 12.92f * v : 1.055f * powf(v, 1.0f / 2.4f) - 0.055f;
 }
 
 }  // namespace vrn

@@ -71,7 +71,8 @@ struct RenderArgs {
   float* rgba;               // [n_cams][H][W][4]
   uint32_t* nsamples;        // nullable
   uint8_t* ws;               // workspace
-  int32_t linear_hdr;
+  int32_t output;            // vrn_output
+  float exposure;            // 2^exposure_ev (VRN_OUT_SRGB)
   uint32_t budget;           // march steps per round
 };
 
@@ -85,6 +86,9 @@ hipError_t launch_march(const FieldDev& F, const vrn_camera* d_cams, uint32_t n_
                         uint32_t H, uint32_t* klist, uint32_t max_k, uint32_t* count, hipStream_t s);
 hipError_t launch_encode(const FieldDev& F, const float* xyz, const float* t, const float* r,
                          uint32_t n, float* feat, hipStream_t s);
+hipError_t launch_prune(const FieldDev& F, float alpha, uint32_t npts, int compute, uint32_t* bits_out,
+                        float* max_op, hipStream_t s);
+hipError_t launch_set_occupancy(const FieldDev& F, const uint32_t* bits, hipStream_t s);
 hipError_t launch_mlp(const FieldDev& F, const float* feat, const float* dir, uint32_t n,
                       int compute, float* sigma, float* rgb, hipStream_t s);
 

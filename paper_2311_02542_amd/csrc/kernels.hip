@@ -115,6 +115,7 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
   if (threadIdx.x < F.L) s_lv[threadIdx.x] = F.levels[threadIdx.x];
   if (threadIdx.x < 6) s_stats[threadIdx.x] = 0;
   const uint32_t tx = (A.W + kTile - 1) / kTile;
+  const float inv_tx = 1.0f / (float)tx;
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
     for (uint32_t c = 0; c < A.n_cams; ++c) {
@@ -150,10 +151,15 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
 
   auto retire = [&]() {
     float4 v = make_float4(cr, cg, cb, 1.0f - T);
-    if (A.linear_hdr) {
+    if (A.output != VRN_OUT_PQ) {
       v.x = pq_to_linear(v.x);
       v.y = pq_to_linear(v.y);
       v.z = pq_to_linear(v.z);
+      if (A.output == VRN_OUT_SRGB) {
+        v.x = srgb_oetf(v.x * A.exposure);
+        v.y = srgb_oetf(v.y * A.exposure);
+        v.z = srgb_oetf(v.z * A.exposure);
+      }
     }
     reinterpret_cast<float4*>(A.rgba)[pix] = v;
     if (A.nsamples) A.nsamples[pix] = n;
@@ -184,8 +190,13 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
           while (c + 1 < A.n_cams && id >= s_off[c + 1]) ++c;
           const uint32_t local = id - s_off[c];
           const uint32_t tile = local / (kTile * kTile), within = local % (kTile * kTile);
-          const uint32_t col = (tile % tx) * kTile + within % kTile;
-          const uint32_t row = s_rb[c] + (tile / tx) * kTile + within / kTile;
+          // tile / tx without an integer division: float quotient, then an
+          // exact integer correction (tile < 2^24)
+          uint32_t ty = (uint32_t)((float)tile * inv_tx);
+          if (ty * tx > tile) --ty;
+          else if ((ty + 1) * tx <= tile) ++ty;
+          const uint32_t col = (tile - ty * tx) * kTile + within % kTile;
+          const uint32_t row = s_rb[c] + ty * kTile + within / kTile;
           if (col < A.W && row < s_re[c]) {
             setup_ray(F, A.cams[c], col, row, r);
             if constexpr (MODE != 0) store_ray_sh<MODE == 2>(F, r, &s_sh[threadIdx.x * 4]);
@@ -420,6 +431,131 @@ __global__ __launch_bounds__(kBlock) void mlp_kernel(FieldDev F, const float* fe
 }
 
 // ---------------------------------------------------------------------------
+// grid pruning (Sec. 4.3, App. C): max opacity over points inside each
+// occupied voxel, threshold alpha; pruning only clears bits
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool cell_occupied(const FieldDev& F, uint32_t x, uint32_t y, uint32_t z) {
+  const uint32_t b = (x >> 2) + F.Gb * ((y >> 2) + F.Gb * (z >> 2));
+  const unsigned long long w = F.bricks[b];
+  return (w >> ((x & 3) + 4 * (y & 3) + 16 * (z & 3))) & 1ull;
+}
+
+// offsets of point i inside a voxel: 4 = tetrahedral corners of the 2x2x2
+// sub-lattice at {1/4, 3/4}; otherwise a p^3 grid at (i + 1/2) / p
+__device__ __forceinline__ float voxel_offset(uint32_t npts, uint32_t p, uint32_t i, int axis) {
+  if (npts == 4) {
+    const float q = 0.25f, t = 0.75f;
+    const float tab[4][3] = {{q, q, q}, {t, t, q}, {t, q, t}, {q, t, t}};
+    return tab[i & 3][axis];
+  }
+  const uint32_t c = axis == 0 ? i % p : (axis == 1 ? (i / p) % p : i / (p * p));
+  return ((float)c + 0.5f) / (float)p;
+}
+
+template <bool TAB16, int MODE>
+__global__ __launch_bounds__(kBlock) void prune_kernel(FieldDev F, float alpha, uint32_t npts, uint32_t p,
+                                                      uint32_t* bits_out, float* max_op) {
+  __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
+  __shared__ float s_b[kBiasTotal];
+  __shared__ LevelDev s_lv[kMaxLevels];
+  __shared__ uint32_t s_max[kBlock];
+  __shared__ uint32_t s_slot[kBlock];
+  load_weights<MODE>(F, s_w, s_b);
+  if (threadIdx.x < F.L) s_lv[threadIdx.x] = F.levels[threadIdx.x];
+  s_max[threadIdx.x] = 0u;
+  __syncthreads();
+  const __amdgpu_buffer_rsrc_t tab = table_rsrc(F);
+  const int lane = lane_id(), g = lane >> 4;
+  const int wave_base = (threadIdx.x >> 6) << 6;
+  const uint64_t n = (uint64_t)F.G * F.G * F.G;
+  const uint64_t chunk = blockIdx.x * (uint64_t)(kBlock / 64) + threadIdx.x / 64;
+  const uint64_t v = chunk * 64 + (uint64_t)lane;
+  const uint32_t G = F.G;
+  const uint32_t vx = (uint32_t)(v % G), vy = (uint32_t)((v / G) % G), vz = (uint32_t)(v / ((uint64_t)G * G));
+  const bool occ = v < n && cell_occupied(F, vx, vy, vz);
+  const uint64_t m = __ballot(occ);
+  const int nv = __popcll(m);
+  const int rank = __popcll(m & ((1ull << lane) - 1ull));
+  if (occ) s_slot[wave_base + rank] = (uint32_t)lane;
+  __builtin_amdgcn_wave_barrier();
+  const int ns = nv * (int)npts;
+  const float cell = F.inv_cs;
+  for (int t = 0; t * 16 < ns; ++t) {
+    asm volatile("" ::: "memory");
+    const int s = t * 16 + (lane & 15);
+    const bool act = s < ns;
+    const int vr = act ? s / (int)npts : 0;
+    const uint32_t pi = act ? (uint32_t)(s % (int)npts) : 0u;
+    const int src = act ? (int)s_slot[wave_base + vr] : lane;
+    const uint64_t sv = chunk * 64 + (uint64_t)src;
+    const uint32_t c[3] = {(uint32_t)(sv % G), (uint32_t)((sv / G) % G), (uint32_t)(sv / ((uint64_t)G * G))};
+    float x[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = F.amin[a] + ((float)c[a] + voxel_offset(npts, p, pi, a)) * cell;
+    float feat[8];
+    uint32_t fetches = 0;
+    // every level weighs 1 (no ray, no LOD): L* above the finest level
+    encode_point<TAB16, MODE == 0>(F, s_lv, tab, x, 1.0e9f, act, g, feat, fetches);
+    float shs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float o0, lg[3];
+    run_mlp<MODE>(s_w, s_b, F, feat, shs, lane, o0, lg);
+    if (act && g == 0) {
+      const float op = 1.0f - expf(-expf(o0) * F.dt);
+      atomicMax(&s_max[wave_base + vr], __float_as_uint(fmaxf(op, 0.0f)));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  float mx = 0.0f;
+  if (occ) mx = __uint_as_float(s_max[wave_base + rank]);
+  const bool keep = occ && mx >= alpha;
+  const uint64_t km = __ballot(keep);
+  if (max_op && v < n) max_op[v] = occ ? mx : __builtin_nanf("");
+  if (lane == 0) {
+    const uint64_t words = (n + 31) / 32;
+    if (2 * chunk < words) bits_out[2 * chunk] = (uint32_t)km;
+    if (2 * chunk + 1 < words) bits_out[2 * chunk + 1] = (uint32_t)(km >> 32);
+  }
+}
+
+// Rebuild a resident field's bricks and coarse grid from linear bits.
+__global__ void bricks_from_bits_kernel(FieldDev F, unsigned long long* bricks, const uint32_t* bits) {
+  const uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t nb = (uint64_t)F.Gb * F.Gb * F.Gb;
+  if (b >= nb) return;
+  const uint32_t bx = (uint32_t)(b % F.Gb), by = (uint32_t)((b / F.Gb) % F.Gb), bz = (uint32_t)(b / ((uint64_t)F.Gb * F.Gb));
+  unsigned long long w = 0ull;
+  for (uint32_t i = 0; i < 64; ++i) {
+    const uint32_t x = 4 * bx + (i & 3), y = 4 * by + ((i >> 2) & 3), z = 4 * bz + (i >> 4);
+    if (x < F.G && y < F.G && z < F.G) {
+      const uint64_t idx = x + (uint64_t)F.G * (y + (uint64_t)F.G * z);
+      if ((bits[idx >> 5] >> (idx & 31)) & 1u) w |= 1ull << i;
+    }
+  }
+  bricks[b] = w;
+}
+
+__global__ void coarse_from_bricks_kernel(FieldDev F, uint32_t* coarse) {
+  const uint32_t word = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nc = F.Gc * F.Gc * F.Gc;
+  if (word >= (nc + 31) / 32) return;
+  const uint32_t per = 1u << (F.cshift - 2);   // bricks per coarse block and axis
+  uint32_t out = 0u;
+  for (uint32_t j = 0; j < 32; ++j) {
+    const uint32_t c = word * 32 + j;
+    if (c >= nc) break;
+    const uint32_t cx = c % F.Gc, cy = (c / F.Gc) % F.Gc, cz = c / (F.Gc * F.Gc);
+    bool any = false;
+    for (uint32_t k = 0; k < per * per * per && !any; ++k) {
+      const uint32_t bx = cx * per + k % per, by = cy * per + (k / per) % per, bz = cz * per + k / (per * per);
+      if (bx < F.Gb && by < F.Gb && bz < F.Gb) any = F.bricks[bx + F.Gb * (by + F.Gb * bz)] != 0ull;
+    }
+    if (any) out |= 1u << j;
+  }
+  coarse[word] = out;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -459,6 +595,35 @@ hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t
     else if (compute == 1) hipLaunchKernelGGL((render_kernel<false, 1>), gr, bl, 0, s, a);
     else hipLaunchKernelGGL((render_kernel<false, 2>), gr, bl, 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_prune(const FieldDev& F, float alpha, uint32_t npts, int compute, uint32_t* bits_out,
+                        float* max_op, hipStream_t s) {
+  uint32_t p = 1;
+  while ((p + 1) * (p + 1) * (p + 1) <= npts) ++p;
+  const uint64_t n = (uint64_t)F.G * F.G * F.G;
+  const uint64_t waves = (n + 63) / 64;
+  const dim3 gr((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64))), bl(kBlock);
+  if (F.table_f16) {
+    if (compute == 0) hipLaunchKernelGGL((prune_kernel<true, 0>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+    else if (compute == 1) hipLaunchKernelGGL((prune_kernel<true, 1>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+    else hipLaunchKernelGGL((prune_kernel<true, 2>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+  } else {
+    if (compute == 0) hipLaunchKernelGGL((prune_kernel<false, 0>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+    else if (compute == 1) hipLaunchKernelGGL((prune_kernel<false, 1>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+    else hipLaunchKernelGGL((prune_kernel<false, 2>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_occupancy(const FieldDev& F, const uint32_t* bits, hipStream_t s) {
+  const uint64_t nb = (uint64_t)F.Gb * F.Gb * F.Gb;
+  hipLaunchKernelGGL(bricks_from_bits_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, F,
+                     const_cast<unsigned long long*>(F.bricks), bits);
+  const uint32_t words = (F.Gc * F.Gc * F.Gc + 31) / 32;
+  hipLaunchKernelGGL(coarse_from_bricks_kernel, dim3((words + 255) / 256), dim3(256), 0, s, F,
+                     const_cast<uint32_t*>(F.coarse));
   return hipGetLastError();
 }
 

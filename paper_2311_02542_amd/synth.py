@@ -302,6 +302,67 @@ def field_c4(table_dtype=np.float16) -> dict:
         dt=dt, max_samples=2048, t_min=1e-4, lod_enable=1)
 
 
+def field_unbounded(table_dtype=np.float32) -> dict:
+    """Unbounded scene for the L-infinity contraction: a room in the inner
+    cube (radius 2 m around the origin, 1-cell walls with window openings and
+    furniture boxes) and far-field structure beyond it -- a ground band and a
+    distant shell -- laid out directly in the contracted cube [-2, 2]^3
+    (256^3 cells).  Exponential step schedule beyond 256 steps."""
+    L, log2_T, s, nmax = 16, 19, 16.0, 4096.0
+    f64 = (nmax / s) ** (1.0 / (L - 1))
+    g = 256
+    rng = rng_for(6, 3)
+    occ = np.zeros((g, g, g), bool)
+    lo, hi = g // 4, 3 * g // 4            # inner cube [-1, 1] in contracted units
+    occ[lo, lo:hi, lo:hi] = occ[hi - 1, lo:hi, lo:hi] = True          # floor / ceiling (z)
+    occ[lo:hi, lo, lo:hi] = occ[lo:hi, hi - 1, lo:hi] = True          # walls (y)
+    occ[lo:hi, lo:hi, lo] = occ[lo:hi, lo:hi, hi - 1] = True          # walls (x)
+    for _ in range(6):                      # window openings in the walls
+        a, b = rng.integers(lo + 10, hi - 40, size=2)
+        w = rng.integers(12, 30)
+        side = rng.integers(4)
+        if side == 0:
+            occ[a:a + w, lo, b:b + w] = False
+        elif side == 1:
+            occ[a:a + w, hi - 1, b:b + w] = False
+        elif side == 2:
+            occ[a:a + w, b:b + w, lo] = False
+        else:
+            occ[a:a + w, b:b + w, hi - 1] = False
+    for _ in range(12):                     # furniture boxes on the floor
+        sx, sy, sz = rng.integers(6, 24, size=3)
+        x0, y0 = rng.integers(lo + 2, hi - 2 - 24, size=2)
+        occ[lo + 1:lo + 1 + sz, y0:y0 + sy, x0:x0 + sx] = True
+    c = (np.arange(g) + 0.5) / g * 4.0 - 2.0
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    m = np.maximum(np.maximum(np.abs(x), np.abs(y)), np.abs(z))
+    occ |= (m > 1.0) & (z > -1.05) & (z < -1.0)                       # ground band
+    occ |= m > 1.9                                                     # distant shell
+    dt = np.float32(2.0 * math.sqrt(3.0) / 1024.0)   # world step inside the 4 m room
+    f = _field(
+        name="unbounded", n_levels=L, log2_T=log2_T, level_res=level_resolutions(L, s, f64),
+        base_res=s, growth=float(np.float32(f64)),
+        tables=make_tables(rng_for(6, 1), L, log2_T, "normal", table_dtype),
+        mlp=make_mlp(rng_for(6, 2), L, 4, density_bias(1e-4, 2.3, float(dt))), sh_bands=4,
+        occ_res=g, occ_bits=pack_bits(occ), aabb_min=[-2.0, -2.0, -2.0], extent=4.0,
+        dt=dt, max_samples=1024, t_min=1e-4, lod_enable=1)
+    f.update(contraction=1, center=np.zeros(3, np.float32), radius=2.0,
+             inv_radius=float(np.float32(1.0 / 2.0)), step_growth=float(np.float32(1.0 / 256.0)),
+             max_lattice=1600)
+    return f
+
+
+def cameras_unbounded(n=2, W=256, H=256):
+    rng = rng_for(6, 4)
+    out = []
+    for _ in range(n):
+        xy = rng.uniform(-1.2, 1.2, 2)
+        yaw = rng.uniform(0, 2 * math.pi)
+        out.append(camera(look_rotation(yaw, math.radians(rng.uniform(-10, 20))),
+                          np.array([xy[0], xy[1], -0.4]), W, H, 90.0))
+    return out
+
+
 def field_c5c() -> dict:
     """Serving scene C: config-2 architecture with T=2^20 and FP16 tables."""
     return field_c2(log2_T=20, table_dtype=np.float16, config=5)
@@ -443,7 +504,7 @@ def request_cameras(scene: str, kind: str, pose_seed: int):
 
 _SCALARS = ("name", "n_levels", "log2_T", "n_feat", "base_res", "growth", "sh_bands",
             "occ_res", "extent", "dt", "max_samples", "t_min", "lod_enable", "lod_bias",
-            "lod_radius_scale")
+            "lod_radius_scale", "contraction", "radius", "inv_radius", "step_growth", "max_lattice")
 
 
 def save_field(prefix: str, field: dict) -> None:
@@ -453,7 +514,9 @@ def save_field(prefix: str, field: dict) -> None:
     for k, v in field["mlp"].items():
         arrays["mlp_" + k] = v
     np.savez(prefix + ".npz", **arrays)
-    meta = {k: (field[k].item() if hasattr(field[k], "item") else field[k]) for k in _SCALARS}
+    meta = {k: (field[k].item() if hasattr(field[k], "item") else field[k]) for k in _SCALARS if k in field}
+    if "center" in field:
+        meta["center"] = [float(v) for v in np.asarray(field["center"], np.float32)]
     meta["format"] = "vrn-field-1"
     meta["table_dtype"] = str(np.dtype(field["tables"].dtype))
     meta["sh_convention"] = "real, no Condon-Shortley phase, bands 0..n-1, order (l, m=-l..l)"

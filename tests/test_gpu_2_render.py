@@ -148,3 +148,21 @@ def test_deterministic_and_workspace_reuse(R):
     assert np.array_equal(a1, a2) and np.array_equal(n1, n2)
     assert np.array_equal(a1, rgba.cpu().numpy()) and np.array_equal(n1, ns.cpu().numpy())
     assert st["rays"] == 256 * 256 and st["samples"] == int(n1.sum())
+
+
+@pytest.mark.parametrize("ev", [-2.0, 0.0, 3.5])
+def test_srgb_display_output(R, ev):
+    from oracle.pq import pq_to_display
+    f = synth.field_c1()
+    cams = synth.cameras_c1(3)
+    fid = R.load(f)
+    disp, _ = R.render(fid, cams, 64, 64, "f32", output="srgb", exposure_ev=ev)
+    R.torch.cuda.synchronize()
+    R.unload(fid)
+    ref = render_fp64(f, cams, 64, 64)
+    want = pq_to_display(ref["rgba"][:, :3], ev)
+    got = disp.cpu().numpy().reshape(-1, 4)
+    ok = ~ref["tie"]
+    err = np.abs(got[ok, :3] - want[ok]).max()
+    assert err <= 2e-5, err
+    np.testing.assert_allclose(got[:, 3], ref["rgba"][:, 3], atol=1e-5)

@@ -86,3 +86,16 @@ def test_lod_bias_shifts_level_exactly_and_clamps():
     # L* doubles footprint -> drops exactly one "octave" of log_f 2 levels
     l2 = level_star(2 * t, r, base)
     np.testing.assert_allclose(l0 - l2, math.log(2) / math.log(np.float32(1.5)), atol=1e-9)
+
+
+def test_srgb_transfer_reference_points_and_tonemap():
+    g = json.load(open(os.path.join(GOLD, "srgb_points.json")))
+    for lin, enc in g["points"]:
+        assert abs(float(pq.srgb_oetf(lin)) - enc) <= g["tolerance"], (lin, enc)
+    v = np.linspace(0, 1, 10001)
+    s = pq.srgb_oetf(v)
+    assert np.all(np.diff(s) > 0)
+    # exposure: +1 EV doubles the linear value before the curve; clipping above 1
+    e = pq.linear_to_pq(np.array([0.1, 0.3, 2.0]))
+    np.testing.assert_allclose(pq.pq_to_display(e, 1.0), pq.srgb_oetf(2 * np.array([0.1, 0.3, 2.0])), atol=1e-12)
+    assert abs(pq.pq_to_display(e, 0.0)[2] - 1.0) < 1e-12
