@@ -84,6 +84,17 @@ typedef struct {
   int32_t lod_enable;         /* 0: all levels weight 1; 1: Eq. 3 weights */
   float lod_bias;             /* Delta L added to L* (Sec. 4.2.2) */
   float lod_radius_scale;     /* r = scale * distance of adjacent unit-distance ray points */
+  /* unbounded scenes (Sec. 4: L-infinity cubic contraction) and the
+   * exponential sample schedule (Sec. 6: exponential distances) */
+  int32_t contraction;        /* 0: bounded cube; 1: u = (x - center) / radius,
+                                 C(u) = u if |u|inf <= 1 else (2 - 1/|u|inf) u / |u|inf;
+                                 then aabb_min must be -2 and extent 4 */
+  float center[3];
+  float radius;               /* > 0 when contraction = 1 */
+  float step_growth;          /* 0: uniform t_k = (k + 1/2) dt; > 0: FP32 table
+                                 t_0 = dt/2, t_{k+1} = t_k + max(dt, growth t_k);
+                                 contraction requires a table */
+  uint32_t max_lattice;       /* table length, 1..65536, when a table is used */
 } vrn_field_desc;
 
 /* One pinhole camera.  c2w is row-major 3x4 camera-to-world with OpenCV axes

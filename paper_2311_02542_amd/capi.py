@@ -41,7 +41,8 @@ class VrnFieldDesc(ctypes.Structure):
                 ("weights", ctypes.POINTER(c_f)), ("occ_res", c_u32),
                 ("occ_bits", ctypes.POINTER(c_u32)), ("aabb_min", c_f * 3), ("extent", c_f),
                 ("dt", c_f), ("max_samples", c_u32), ("t_min", c_f), ("lod_enable", c_i32),
-                ("lod_bias", c_f), ("lod_radius_scale", c_f)]
+                ("lod_bias", c_f), ("lod_radius_scale", c_f), ("contraction", c_i32),
+                ("center", c_f * 3), ("radius", c_f), ("step_growth", c_f), ("max_lattice", c_u32)]
 
 
 class VrnCamera(ctypes.Structure):
@@ -172,6 +173,11 @@ def make_field_desc(field):
     d.lod_enable = int(bool(field.get("lod_enable", 0)))
     d.lod_bias = float(field.get("lod_bias", 0.0))
     d.lod_radius_scale = float(field.get("lod_radius_scale", 1.0))
+    d.contraction = int(field.get("contraction", 0))
+    d.center[:] = [float(v) for v in np.asarray(field.get("center", np.zeros(3)), np.float32)]
+    d.radius = float(field.get("radius", 1.0))
+    d.step_growth = float(field.get("step_growth", 0.0))
+    d.max_lattice = int(field.get("max_lattice", 0))
     return d, (level_res, tables, weights, occ)
 
 

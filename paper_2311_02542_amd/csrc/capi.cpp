@@ -162,6 +162,18 @@ vrn_status validate_desc(const vrn_field_desc* d) {
   if (d->max_samples < 1) return fail(VRN_ERR_INVALID_ARG, "max_samples must be >= 1");
   if (!finite(d->t_min) || d->t_min < 0.0f || d->t_min >= 1.0f)
     return fail(VRN_ERR_INVALID_ARG, "t_min must be in [0, 1)");
+  if (d->contraction != 0 && d->contraction != 1) return fail(VRN_ERR_INVALID_ARG, "contraction must be 0 or 1");
+  if (!finite(d->step_growth) || d->step_growth < 0.0f || d->step_growth >= 1.0f)
+    return fail(VRN_ERR_INVALID_ARG, "step_growth must be in [0, 1)");
+  if (d->contraction) {
+    for (int a = 0; a < 3; ++a)
+      if (!finite(d->center[a]) || d->aabb_min[a] != -2.0f)
+        return fail(VRN_ERR_INVALID_ARG, "contracted fields need a finite center and aabb_min = -2");
+    if (d->extent != 4.0f) return fail(VRN_ERR_INVALID_ARG, "contracted fields need extent = 4");
+    if (!finite(d->radius) || !(d->radius > 0.0f)) return fail(VRN_ERR_INVALID_ARG, "radius must be > 0");
+  }
+  if ((d->contraction || d->step_growth > 0.0f) && (d->max_lattice < 1 || d->max_lattice > 65536))
+    return fail(VRN_ERR_INVALID_ARG, "max_lattice must be 1..65536 when a sample table is used");
   if (d->lod_enable) {
     if (!finite(d->base_res) || !(d->base_res > 0.0f)) return fail(VRN_ERR_INVALID_ARG, "base_res must be > 0");
     if (!finite(d->growth) || !(d->growth > 1.0f)) return fail(VRN_ERR_INVALID_ARG, "growth must be > 1");
@@ -261,7 +273,7 @@ vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t 
   const int compute = opts ? (int)opts->compute : 0;
   const uint64_t rays = (uint64_t)n_cams * W * H;
   const uint64_t want = (rays + kBlock - 1) / kBlock;
-  const uint64_t cap = (uint64_t)ctx->n_cu * render_blocks_per_cu(f->dev.table_f16, compute);
+  const uint64_t cap = (uint64_t)ctx->n_cu * render_blocks_per_cu(f->dev, compute);
   const int grid = (int)std::max<uint64_t>(1, std::min(want, cap));
   hipError_t e = launch_render(a, compute, grid, s);
   if (e != hipSuccess) return hip_fail(e, "render launch");
@@ -373,6 +385,19 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
     P.s_lo = (float)(S - (double)P.s_hi);
     P.pad = 0;
   }
+  // canonical FP32 sample table (same recurrence, same rounding, as the oracle)
+  const bool use_table = d->contraction || d->step_growth > 0.0f;
+  std::vector<float> lat;
+  if (use_table) {
+    lat.resize((size_t)d->max_lattice + 1);
+    volatile float t = 0.5f * d->dt;   // volatile: every step rounded to FP32
+    lat[0] = t;
+    for (uint32_t k = 0; k < d->max_lattice; ++k) {
+      const float g = d->step_growth * t;
+      t = t + (g > d->dt ? g : d->dt);
+      lat[k + 1] = t;
+    }
+  }
   const uint64_t tab_bytes = n_tab * (d->table_dtype == VRN_F16 ? 2 : 4);
   const uint64_t need = tab_bytes + bricks.size() * 8 + coarse.size() * 4 + (w32.size() + bias.size()) * 4 +
                         (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev);
@@ -387,13 +412,14 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   LevelDev* dlv = nullptr;
   unsigned long long* dbr = nullptr;
   uint32_t* dco = nullptr;
-  float *dw32 = nullptr, *dbias = nullptr;
+  float *dw32 = nullptr, *dbias = nullptr, *dlat = nullptr;
   uint16_t *dw16 = nullptr, *dwbf = nullptr;
   if ((e = upload(f, static_cast<const uint8_t*>(d->tables), tab_bytes, &tab)) ||
       (e = upload(f, lv.data(), lv.size(), &dlv)) || (e = upload(f, bricks.data(), bricks.size(), &dbr)) ||
       (e = upload(f, coarse.data(), coarse.size(), &dco)) || (e = upload(f, w32.data(), w32.size(), &dw32)) ||
       (e = upload(f, w16.data(), w16.size(), &dw16)) || (e = upload(f, wbf.data(), wbf.size(), &dwbf)) ||
-      (e = upload(f, bias.data(), bias.size(), &dbias))) {
+      (e = upload(f, bias.data(), bias.size(), &dbias)) ||
+      (use_table && (e = upload(f, lat.data(), lat.size(), &dlat)))) {
     free_field(f);
     return e == hipErrorOutOfMemory ? fail(VRN_ERR_OUT_OF_MEMORY, "device allocation failed")
                                     : hip_fail(e, "field upload");
@@ -429,6 +455,13 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.lod_bias = d->lod_bias;
   F.lod_radius_scale = d->lod_enable ? d->lod_radius_scale : 1.0f;
   F.d1_ksteps = L > 8 ? 8u : 4u;
+  F.lat = dlat;
+  F.lat_K = use_table ? d->max_lattice : 0u;
+  F.contract = d->contraction;
+  for (int a = 0; a < 3; ++a) F.center[a] = d->center[a];
+  F.radius = d->contraction ? d->radius : 1.0f;
+  F.inv_radius = d->contraction ? (float)(1.0 / (double)d->radius) : 1.0f;
+  F.lod_c2 = d->lod_enable ? (float)std::log(2.0 * (double)d->base_res) : 0.0f;
   F.dense_mask = 0;
   for (uint32_t l = 0; l < L; ++l) F.dense_mask |= lv[l].dense << l;
   F.c1_ksteps = 8u;

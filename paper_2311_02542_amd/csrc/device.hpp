@@ -53,6 +53,7 @@ struct Ray {
   int k, k_hi;   // lattice cursor and last lattice index worth testing
   int brick;     // index of the 4x4x4 brick whose bits are cached below (-1: none)
   uint32_t blo, bhi;
+  float nx, ny, nz;  // right neighbour's direction (contracted LOD footprint)
 };
 
 // Canonical FP32 direction: a = ((i + .5) - cx) / fx, b = ((j + .5) - cy) / fy,
@@ -86,11 +87,34 @@ __device__ __forceinline__ float cone_pitch(const vrn_camera& c, const float w[3
   return scale * sn * __builtin_amdgcn_rsqf(0.5f * (1.0f + cs));
 }
 
+// Number of table entries <= t (binary search over the canonical FP32 table).
+__device__ __forceinline__ int table_count_le(const FieldDev& F, float t) {
+  int lo = 0, hi = (int)F.lat_K;   // answer in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (F.lat[mid] <= t) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Lattice range [k_lo, k_hi] from an FP32 slab test padded by two steps on
-// each side; the canonical per-sample test alone decides membership.
+// each side; the canonical per-sample test alone decides membership.  With a
+// sample table the padded slab is mapped through the table; contracted
+// fields keep every table sample (all of space lies in the cube).
+template <int GEO>
 __device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
   const float o[3] = {r.ox, r.oy, r.oz};
   const float d[3] = {r.dx, r.dy, r.dz};
+  const float kmax = 16777000.0f;  // keep k < 2^24 (k + 0.5 exact in FP32)
+  if (GEO == 1 && F.contract) {
+    r.k = 0;
+    r.k_hi = (int)F.lat_K - 1;
+    const float M = (fmaxf(fabsf(o[0] - F.center[0]), fmaxf(fabsf(o[1] - F.center[1]), fabsf(o[2] - F.center[2]))) +
+                     F.lat[F.lat_K - 1]) * F.inv_radius + 2.0f;
+    r.delta = ldexpf(F.cs * M + (float)F.G + 1.0f, -20);
+    return;
+  }
   float tn = 0.0f, tf = 3.0e38f;
   bool miss = false;
 #pragma unroll
@@ -105,21 +129,33 @@ __device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
       miss = true;
     }
   }
-  const float kmax = 16777000.0f;  // keep k < 2^24 (k + 0.5 exact in FP32)
-  const float klo = floorf(tn * F.inv_dt - 0.5f) - 2.0f;
-  const float khi = ceilf(fminf(tf * F.inv_dt, kmax) - 0.5f) + 2.0f;
-  if (miss || !(tf >= tn - 2.0f * F.dt) || klo > kmax) {
-    r.k = 0;
-    r.k_hi = -1;
+  if constexpr (GEO == 0) {
+    const float klo = floorf(tn * F.inv_dt - 0.5f) - 2.0f;
+    const float khi = ceilf(fminf(tf * F.inv_dt, kmax) - 0.5f) + 2.0f;
+    if (miss || !(tf >= tn - 2.0f * F.dt) || klo > kmax) {
+      r.k = 0;
+      r.k_hi = -1;
+    } else {
+      r.k = (int)fmaxf(klo, 0.0f);
+      r.k_hi = (int)fminf(khi, kmax);
+    }
   } else {
-    r.k = (int)fmaxf(klo, 0.0f);
-    r.k_hi = (int)fminf(khi, kmax);
+    if (miss || !(tf >= tn - 2.0f * F.dt)) {
+      r.k = 0;
+      r.k_hi = -1;
+    } else {
+      const float pad = 2.0f * F.dt + 1e-5f * tf;
+      r.k = max(table_count_le(F, tn - pad) - 1, 0);
+      r.k_hi = min(table_count_le(F, fminf(tf + pad, 3.0e38f)), (int)F.lat_K - 1);
+    }
   }
-  const float M = fmaxf(fabsf(o[0]), fmaxf(fabsf(o[1]), fabsf(o[2]))) + fminf(tf, kmax * F.dt) +
+  const float tcap = GEO == 0 ? kmax * F.dt : F.lat[F.lat_K - 1];
+  const float M = fmaxf(fabsf(o[0]), fmaxf(fabsf(o[1]), fabsf(o[2]))) + fminf(tf, tcap) +
                   fmaxf(fabsf(F.amin[0]), fmaxf(fabsf(F.amin[1]), fabsf(F.amin[2])));
   r.delta = ldexpf(F.cs * M + (float)F.G + 1.0f, -20);
 }
 
+template <int GEO>
 __device__ __forceinline__ void setup_ray(const FieldDev& F, const vrn_camera& c, uint32_t col,
                                           uint32_t row, Ray& r) {
   float w[3], n, d[3];
@@ -131,22 +167,55 @@ __device__ __forceinline__ void setup_ray(const FieldDev& F, const vrn_camera& c
   r.dy = d[1];
   r.dz = d[2];
   r.lr = F.lod ? __logf(cone_pitch(c, w, n, F.lod_radius_scale)) + F.lod_c : 0.0f;
+  r.nx = r.ny = r.nz = 0.0f;
+  if (GEO == 1 && F.contract && F.lod) {
+    float w2[3], n2, d2[3];
+    canonical_ray(c, col + 1, row, w2, n2, d2);
+    r.nx = d2[0];
+    r.ny = d2[1];
+    r.nz = d2[2];
+  }
   r.brick = -1;
   r.blo = r.bhi = 0u;
-  lattice_range(F, r);
+  lattice_range<GEO>(F, r);
 }
 
 // ---------------------------------------------------------------------------
 // Occupancy march (Sec. 4.3)
 // ---------------------------------------------------------------------------
 
-// Canonical lattice sample k: t = (k + .5) dt, x = o + t d, q = (x - amin) cs.
+// Canonical L-infinity contraction of a world point, in place: u = (x - c)
+// * inv_radius, m = max |u|, y = u if m <= 1 else u * ((2 - 1/m) * (1/m)).
+__device__ __forceinline__ void contract_point(const FieldDev& F, float x[3]) {
+  const float u[3] = {(x[0] - F.center[0]) * F.inv_radius, (x[1] - F.center[1]) * F.inv_radius,
+                      (x[2] - F.center[2]) * F.inv_radius};
+  const float m = fmaxf(fmaxf(fabsf(u[0]), fabsf(u[1])), fabsf(u[2]));
+  if (m <= 1.0f) {
+    x[0] = u[0];
+    x[1] = u[1];
+    x[2] = u[2];
+  } else {
+    const float im = 1.0f / m;
+    const float s = (2.0f - im) * im;
+    x[0] = u[0] * s;
+    x[1] = u[1] * s;
+    x[2] = u[2] * s;
+  }
+}
+
+// Canonical lattice sample k: t = (k + .5) dt (or the FP32 table entry),
+// x = o + t d (contracted for unbounded fields), q = (x - amin) cs.
+template <int GEO>
 __device__ __forceinline__ void lattice_q(const FieldDev& F, const Ray& r, int k, float& t, float x[3],
                                           float q[3]) {
-  t = ((float)k + 0.5f) * F.dt;
+  if constexpr (GEO == 0) t = ((float)k + 0.5f) * F.dt;
+  else t = F.lat[k];
   x[0] = r.ox + t * r.dx;
   x[1] = r.oy + t * r.dy;
   x[2] = r.oz + t * r.dz;
+  if constexpr (GEO == 1) {
+    if (F.contract) contract_point(F, x);
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) q[a] = (x[a] - F.amin[a]) * F.cs;
 }
@@ -165,29 +234,46 @@ __device__ __forceinline__ bool bit_set(const uint32_t* bits, uint32_t idx) {
 // box: by convexity every lattice sample in between lies in it too, and
 // delta >= twice the FP32 error of q, so no sample whose canonical cell is
 // occupied is ever passed.  Returns true if r.k moved.
+template <int GEO>
 __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float q[3], int ox, int oy, int oz,
                                          float size) {
   const float lo[3] = {ox * size + r.delta, oy * size + r.delta, oz * size + r.delta};
   const float hi[3] = {(ox + 1) * size - r.delta, (oy + 1) * size - r.delta, (oz + 1) * size - r.delta};
   if (!(q[0] >= lo[0] && q[0] <= hi[0] && q[1] >= lo[1] && q[1] <= hi[1] && q[2] >= lo[2] && q[2] <= hi[2]))
     return false;
-  const float o[3] = {r.ox, r.oy, r.oz};
-  const float d[3] = {r.dx, r.dy, r.dz};
+  if (GEO == 1 && F.contract) {
+    // only boxes inside the identity region (|u|inf <= 1: q in [G/4, 3G/4])
+    // map straight segments to straight segments
+    const float a = 0.25f * (float)F.G, b = 0.75f * (float)F.G;
+    if (!(ox * size >= a && oy * size >= a && oz * size >= a && (ox + 1) * size <= b && (oy + 1) * size <= b &&
+          (oz + 1) * size <= b))
+      return false;
+  }
   // approximate exit parameter (reciprocals need not be exact: the landing
   // sample is re-tested with the canonical arithmetic below)
+  const float o[3] = {r.ox, r.oy, r.oz};
+  const float d[3] = {r.dx, r.dy, r.dz};
   float te = 3.0e38f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float bq = signbit(d[a]) ? lo[a] : hi[a];
-    te = fminf(te, (bq * F.inv_cs + F.amin[a] - o[a]) * __builtin_amdgcn_rcpf(d[a]));
+    float xb = bq * F.inv_cs + F.amin[a];
+    if (GEO == 1 && F.contract) xb = xb * F.radius + F.center[a];
+    te = fminf(te, (xb - o[a]) * __builtin_amdgcn_rcpf(d[a]));
   }
-  const float kbf = fminf(floorf(te * F.inv_dt - 0.5f), (float)r.k_hi);
-  if (!(kbf >= (float)r.k + 2.0f)) return false;
-  int kb = (int)kbf;
+  int kb;
+  if constexpr (GEO == 0) {
+    const float kbf = fminf(floorf(te * F.inv_dt - 0.5f), (float)r.k_hi);
+    if (!(kbf >= (float)r.k + 2.0f)) return false;
+    kb = (int)kbf;
+  } else {
+    kb = min(table_count_le(F, te) - 1, r.k_hi);
+    if (kb < r.k + 2) return false;
+  }
 #pragma unroll
   for (int tries = 0; tries < 2; ++tries, --kb) {
     float t2, x2[3], q2[3];
-    lattice_q(F, r, kb, t2, x2, q2);
+    lattice_q<GEO>(F, r, kb, t2, x2, q2);
     if (q2[0] >= lo[0] && q2[0] <= hi[0] && q2[1] >= lo[1] && q2[1] <= hi[1] && q2[2] >= lo[2] &&
         q2[2] <= hi[2]) {
       r.k = kb + 1;
@@ -203,6 +289,7 @@ __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float 
 // grid (blocks of 2^cshift cells, in LDS), then the 4x4x4 brick (one 64-bit
 // load, kept in registers while the ray stays in the brick), then the cell
 // bit.  Empty coarse blocks and empty bricks are skipped with skip_box.
+template <int GEO>
 __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coarse, Ray& r, uint32_t budget,
                                           uint32_t& steps, float& st, float sx[3]) {
   const int G = (int)F.G;
@@ -211,7 +298,7 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
     if (r.k > r.k_hi) return 2;
     ++steps;
     float t, x[3], q[3];
-    lattice_q(F, r, r.k, t, x, q);
+    lattice_q<GEO>(F, r, r.k, t, x, q);
     const int cx = cell_of(q[0], G), cy = cell_of(q[1], G), cz = cell_of(q[2], G);
     // empty box to try to jump over: origin (in units of its size) and size
     int bo[3] = {0, 0, 0};
@@ -251,7 +338,7 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
         }
       }
     }
-    const bool moved = bsize > 0.0f && skip_box(F, r, q, bo[0], bo[1], bo[2], bsize);
+    const bool moved = bsize > 0.0f && skip_box<GEO>(F, r, q, bo[0], bo[1], bo[2], bsize);
     if (!moved) r.k++;
   }
   return 0;
@@ -401,6 +488,24 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     feat[2 * j + 1] = w * acc1;
     ++fetches;
   }
+}
+
+// Step length of lattice sample k (uniform lattice or FP32 table).
+template <int GEO>
+__device__ __forceinline__ float sample_step(const FieldDev& F, int k) {
+  if constexpr (GEO == 0) return F.dt;
+  else return F.lat[k + 1] - F.lat[k];
+}
+
+// L* of a sample of a contracted field: the footprint is the distance between
+// the corresponding points of this ray and its right neighbour in contracted
+// space (Sec. 4.2.1), in normalised units (the cube edge is 4).
+__device__ __forceinline__ float level_star_contracted(const FieldDev& F, const Ray& r, float t, const float y[3]) {
+  float yn[3] = {r.ox + t * r.nx, r.oy + t * r.ny, r.oz + t * r.nz};
+  contract_point(F, yn);
+  const float dx = yn[0] - y[0], dy = yn[1] - y[1], dz = yn[2] - y[2];
+  const float rhat = F.lod_radius_scale * 0.25f * __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+  return fmaxf(-(__logf(rhat) + F.lod_c2) * F.inv_ln_f + F.lod_bias, 0.0f);
 }
 
 // Optimal LOD level L* = -log_f(2 s r_hat) + bias, clamped at 0 (Sec. 4.2.1-2),

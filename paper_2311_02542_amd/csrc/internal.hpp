@@ -53,6 +53,12 @@ struct FieldDev {
   float lod_c;               // ln(2 s / extent)
   float lod_bias, lod_radius_scale;
   uint32_t dense_mask;       // bit l set: level l is stored densely
+  // table lattice / contraction (GEO = 1 kernels)
+  const float* lat;          // t_0 .. t_K (K + 1 entries), canonical FP32
+  uint32_t lat_K;            // number of lattice samples
+  int32_t contract;          // L-infinity contraction on
+  float center[3], inv_radius, radius;
+  float lod_c2;              // ln(2 s): LOD constant when the footprint is already normalised
   uint32_t d1_ksteps;        // FP32 k-steps of the first density layer
   uint32_t c1_ksteps;        // FP32 k-steps of the first color layer
 };
@@ -78,7 +84,7 @@ struct RenderArgs {
 
 // launchers (kernels.hip)
 hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t s);
-int render_blocks_per_cu(int table_f16, int compute);
+int render_blocks_per_cu(const FieldDev& F, int compute);
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
 hipError_t launch_rays(const vrn_camera* d_cams, uint32_t n_cams, uint32_t W, uint32_t H,
                        float scale, float* o, float* d, float* r, hipStream_t s);

@@ -96,7 +96,7 @@ __device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, ui
   }
 }
 
-template <bool TAB16, int MODE>
+template <bool TAB16, int MODE, int GEO>
 __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(RenderArgs A) {
   __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
   __shared__ float s_b[kBiasTotal];
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
           const uint32_t col = (tile - ty * tx) * kTile + within % kTile;
           const uint32_t row = s_rb[c] + ty * kTile + within / kTile;
           if (col < A.W && row < s_re[c]) {
-            setup_ray(F, A.cams[c], col, row, r);
+            setup_ray<GEO>(F, A.cams[c], col, row, r);
             if constexpr (MODE != 0) store_ray_sh<MODE == 2>(F, r, &s_sh[threadIdx.x * 4]);
             pix = (c * A.H + row) * A.W + col;
             T = 1.0f;
@@ -217,11 +217,14 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
 
     // ---- 2. march to the next evaluated sample ---------------------------
     int mres = 0;
-    float st = 0.0f, sx[3] = {0.0f, 0.0f, 0.0f}, slst = 0.0f;
+    float st = 0.0f, sx[3] = {0.0f, 0.0f, 0.0f}, slst = 0.0f, sdt = F.dt;
     if (pix != kNone) {
-      mres = march_next(F, s_coarse, r, A.budget, st_steps, st, sx);
+      mres = march_next<GEO>(F, s_coarse, r, A.budget, st_steps, st, sx);
       if (mres == 2) retire();
-      if (mres == 1 && F.lod) slst = level_star(F, st, r.lr);
+      if (mres == 1) {
+        if (F.lod) slst = (GEO == 1 && F.contract) ? level_star_contracted(F, r, st, sx) : level_star(F, st, r.lr);
+        sdt = sample_step<GEO>(F, r.k - 1);
+      }
     }
     const bool has = mres == 1;
     const uint64_t m = __ballot(has);
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
 
     // ---- 4. composite (FP32), terminate --------------------------------
     if (has) {
-      const float sd = expf(so0) * F.dt;
+      const float sd = expf(so0) * sdt;
       const float trans = expf(-sd);
       const float wgt = T * (1.0f - trans);
       cr = fmaf(wgt, sigmoidf(sl0), cr);
@@ -354,6 +357,7 @@ __global__ void rays_kernel(const vrn_camera* cams, uint32_t n_cams, uint32_t W,
   rr[i] = cone_pitch(cams[c], w, nn, scale);
 }
 
+template <int GEO>
 __global__ void march_kernel(FieldDev F, const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H,
                              uint32_t* klist, uint32_t max_k, uint32_t* count) {
   __shared__ uint32_t s_coarse[kCoarseWords];
@@ -364,11 +368,11 @@ __global__ void march_kernel(FieldDev F, const vrn_camera* cams, uint32_t n_cams
   const uint32_t c = (uint32_t)(i / ((uint64_t)W * H));
   const uint32_t rem = (uint32_t)(i % ((uint64_t)W * H));
   Ray r;
-  setup_ray(F, cams[c], rem % W, rem / W, r);
+  setup_ray<GEO>(F, cams[c], rem % W, rem / W, r);
   uint32_t cnt = 0, steps = 0;
   float st, sx[3];
   while (cnt < F.max_samples) {
-    if (march_next(F, s_coarse, r, 0x40000000u, steps, st, sx) != 1) break;
+    if (march_next<GEO>(F, s_coarse, r, 0x40000000u, steps, st, sx) != 1) break;
     if (cnt < max_k) klist[i * max_k + cnt] = (uint32_t)(r.k - 1);
     ++cnt;
   }
@@ -559,12 +563,12 @@ __global__ void coarse_from_bricks_kernel(FieldDev F, uint32_t* coarse) {
 // launchers
 // ---------------------------------------------------------------------------
 
-template <bool TAB16, int MODE>
+template <bool TAB16, int MODE, int GEO>
 static int blocks_per_cu_impl() {
   static int cached = -1;
   if (cached < 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, render_kernel<TAB16, MODE>, kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, render_kernel<TAB16, MODE, GEO>, kBlock, 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
@@ -573,28 +577,39 @@ static int blocks_per_cu_impl() {
   return cached;
 }
 
-int render_blocks_per_cu(int table_f16, int compute) {
+template <int GEO>
+static int blocks_per_cu_geo(int table_f16, int compute) {
   if (table_f16) {
-    if (compute == 0) return blocks_per_cu_impl<true, 0>();
-    if (compute == 1) return blocks_per_cu_impl<true, 1>();
-    return blocks_per_cu_impl<true, 2>();
+    if (compute == 0) return blocks_per_cu_impl<true, 0, GEO>();
+    if (compute == 1) return blocks_per_cu_impl<true, 1, GEO>();
+    return blocks_per_cu_impl<true, 2, GEO>();
   }
-  if (compute == 0) return blocks_per_cu_impl<false, 0>();
-  if (compute == 1) return blocks_per_cu_impl<false, 1>();
-  return blocks_per_cu_impl<false, 2>();
+  if (compute == 0) return blocks_per_cu_impl<false, 0, GEO>();
+  if (compute == 1) return blocks_per_cu_impl<false, 1, GEO>();
+  return blocks_per_cu_impl<false, 2, GEO>();
+}
+
+int render_blocks_per_cu(const FieldDev& F, int compute) {
+  return F.lat ? blocks_per_cu_geo<1>(F.table_f16, compute) : blocks_per_cu_geo<0>(F.table_f16, compute);
+}
+
+template <int GEO>
+static void launch_render_geo(const RenderArgs& a, int compute, dim3 gr, dim3 bl, hipStream_t s) {
+  if (a.F.table_f16) {
+    if (compute == 0) hipLaunchKernelGGL((render_kernel<true, 0, GEO>), gr, bl, 0, s, a);
+    else if (compute == 1) hipLaunchKernelGGL((render_kernel<true, 1, GEO>), gr, bl, 0, s, a);
+    else hipLaunchKernelGGL((render_kernel<true, 2, GEO>), gr, bl, 0, s, a);
+  } else {
+    if (compute == 0) hipLaunchKernelGGL((render_kernel<false, 0, GEO>), gr, bl, 0, s, a);
+    else if (compute == 1) hipLaunchKernelGGL((render_kernel<false, 1, GEO>), gr, bl, 0, s, a);
+    else hipLaunchKernelGGL((render_kernel<false, 2, GEO>), gr, bl, 0, s, a);
+  }
 }
 
 hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t s) {
   const dim3 gr(grid), bl(kBlock);
-  if (a.F.table_f16) {
-    if (compute == 0) hipLaunchKernelGGL((render_kernel<true, 0>), gr, bl, 0, s, a);
-    else if (compute == 1) hipLaunchKernelGGL((render_kernel<true, 1>), gr, bl, 0, s, a);
-    else hipLaunchKernelGGL((render_kernel<true, 2>), gr, bl, 0, s, a);
-  } else {
-    if (compute == 0) hipLaunchKernelGGL((render_kernel<false, 0>), gr, bl, 0, s, a);
-    else if (compute == 1) hipLaunchKernelGGL((render_kernel<false, 1>), gr, bl, 0, s, a);
-    else hipLaunchKernelGGL((render_kernel<false, 2>), gr, bl, 0, s, a);
-  }
+  if (a.F.lat) launch_render_geo<1>(a, compute, gr, bl, s);
+  else launch_render_geo<0>(a, compute, gr, bl, s);
   return hipGetLastError();
 }
 
@@ -646,8 +661,12 @@ hipError_t launch_rays(const vrn_camera* d_cams, uint32_t n_cams, uint32_t W, ui
 hipError_t launch_march(const FieldDev& F, const vrn_camera* d_cams, uint32_t n_cams, uint32_t W,
                         uint32_t H, uint32_t* klist, uint32_t max_k, uint32_t* count, hipStream_t s) {
   const uint64_t n = (uint64_t)n_cams * W * H;
-  hipLaunchKernelGGL(march_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, F, d_cams, n_cams, W,
-                     H, klist, max_k, count);
+  if (F.lat)
+    hipLaunchKernelGGL(march_kernel<1>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, F, d_cams, n_cams, W,
+                       H, klist, max_k, count);
+  else
+    hipLaunchKernelGGL(march_kernel<0>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, F, d_cams, n_cams, W,
+                       H, klist, max_k, count);
   return hipGetLastError();
 }
 
