@@ -375,15 +375,18 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   for (uint32_t l = 0; l < L; ++l) {
     const uint64_t N = d->level_res[l], s = N + 1;
     LevelDev& P = lv[l];
-    P.N = (uint32_t)N;
+    const uint32_t esize = d->table_dtype == VRN_F16 ? 4u : 8u;   // one entry: two features
+    P.top = (float)(N - 1);
     P.dense = (s * s * s <= T) ? 1u : 0u;
-    P.mx = P.dense ? 1u : d->hash_primes[0];
-    P.my = P.dense ? (uint32_t)s : d->hash_primes[1];
-    P.mz = P.dense ? (uint32_t)(s * s) : d->hash_primes[2];
+    P.bx = (P.dense ? 1u : d->hash_primes[0]) * esize;
+    P.by = (P.dense ? (uint32_t)s : d->hash_primes[1]) * esize;
+    P.bz = (P.dense ? (uint32_t)(s * s) : d->hash_primes[2]) * esize;
     const double S = (double)N / (double)d->extent;
     P.s_hi = (float)S;
     P.s_lo = (float)(S - (double)P.s_hi);
-    P.pad = 0;
+    P.base = (uint32_t)((uint64_t)l * T * esize);
+    P.below_n = std::nextafter((float)N, 0.0f);
+    P.pad[0] = P.pad[1] = P.pad[2] = 0u;
   }
   // canonical FP32 sample table (same recurrence, same rounding, as the oracle)
   const bool use_table = d->contraction || d->step_growth > 0.0f;
@@ -436,6 +439,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.log2T = d->log2_T;
   F.Tmask = (uint32_t)(T - 1);
   F.table_f16 = d->table_dtype == VRN_F16;
+  F.bmask = F.Tmask * (F.table_f16 ? 4u : 8u);
   F.G = G;
   F.Gb = Gb;
   F.Gc = Gc;

@@ -387,13 +387,44 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const FieldDev& F) 
 }
 
 // Base corner and fraction from a plain FP32 p = u * S (the 16-bit paths,
-// whose error budget is far above the rounding of p).
-__device__ __forceinline__ uint32_t base_corner_fast(float u, float shi, float top, float& fr) {
-  const float p = u * shi;
-  const float fi = floorf(p);
-  const float ipc = __builtin_amdgcn_fmed3f(fi, 0.0f, top);
-  fr = (p - fi) + (fi - ipc);
-  return (uint32_t)ipc;
+// whose error budget is far above the rounding of p).  p is clamped to
+// [0, below_n], so p = N yields the last cell with fraction 1 - ulp(N).
+__device__ __forceinline__ uint32_t base_corner_fast(float u, float shi, float below_n, float& fr) {
+  const float p = __builtin_amdgcn_fmed3f(u * shi, 0.0f, below_n);
+  fr = __builtin_amdgcn_fractf(p);
+  return (uint32_t)p;
+}
+
+// Byte offsets of the 8 corners of the cell with base corner i0 (corner c:
+// +1 on x if c & 1, on y if c & 2, on z if c & 4).  Dense levels index
+// x + y s + z s^2; hashed levels take (x pi_x ^ y pi_y ^ z pi_z) mod T (the
+// iNGP hash).  The multipliers carry the entry size, so the mask is applied
+// in bytes, and the level's base offset is a multiple of the level size, so
+// it can be OR-ed into the masked hash.  grp (bit g: level g + 4j of lane
+// group g is dense) is wave-uniform: a set of four levels that is all hashed
+// or all dense takes one formula.
+__device__ __forceinline__ void corner_offsets(const FieldDev& F, const LevelDev& P, uint32_t grp,
+                                               const uint32_t i0[3], uint32_t off[8]) {
+  const uint32_t hx0 = i0[0] * P.bx, hx1 = hx0 + P.bx;
+  const uint32_t hy0 = i0[1] * P.by, hy1 = hy0 + P.by;
+  const uint32_t hz0 = i0[2] * P.bz, hz1 = hz0 + P.bz;
+  const uint32_t m = F.bmask;
+  if (grp == 0u) {
+    const uint32_t x0 = (hx0 & m) | P.base, x1 = (hx1 & m) | P.base;
+    const uint32_t y0 = hy0 & m, y1 = hy1 & m, z0 = hz0 & m, z1 = hz1 & m;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) off[c] = ((c & 1) ? x1 : x0) ^ ((c & 2) ? y1 : y0) ^ ((c & 4) ? z1 : z0);
+  } else if (grp == 0xFu) {
+    const uint32_t x0 = hx0 + P.base, x1 = hx1 + P.base;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) off[c] = ((c & 1) ? x1 : x0) + ((c & 2) ? hy1 : hy0) + ((c & 4) ? hz1 : hz0);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t a = (c & 1) ? hx1 : hx0, b = (c & 2) ? hy1 : hy0, e = (c & 4) ? hz1 : hz0;
+      off[c] = P.dense ? (a + b + e) + P.base : (((a ^ b ^ e) & m) | P.base);
+    }
+  }
 }
 
 // Lane (sample, level group g) encodes levels g, g+4, g+8, g+12 of one point.
@@ -412,8 +443,6 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     if constexpr (PRECISE) two_diff(x[a], F.amin[a], uh[a], ul[a]);
     else uh[a] = x[a] - F.amin[a];
   }
-  const uint32_t T = F.Tmask + 1u;
-  constexpr uint32_t kShift = TAB16 ? 2u : 3u;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     feat[2 * j] = 0.0f;
@@ -423,39 +452,15 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     const float w = F.lod ? __builtin_amdgcn_fmed3f(lstar + 1.0f - (float)lev, 0.0f, 1.0f) : 1.0f;
     if (!(w > 0.0f)) continue;
     const LevelDev P = lv[lev];
-    const float top = (float)(P.N - 1u);
     float fr[3];
     uint32_t i0[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if constexpr (PRECISE) i0[a] = base_corner(uh[a], ul[a], P.s_hi, P.s_lo, top, fr[a]);
-      else i0[a] = base_corner_fast(uh[a], P.s_hi, top, fr[a]);
+      if constexpr (PRECISE) i0[a] = base_corner(uh[a], ul[a], P.s_hi, P.s_lo, P.top, fr[a]);
+      else i0[a] = base_corner_fast(uh[a], P.s_hi, P.below_n, fr[a]);
     }
-    const uint32_t grp = (F.dense_mask >> (4 * j)) & 0xFu;   // wave-uniform
-    const uint32_t base = ((uint32_t)lev * T) << kShift;
     uint32_t off[8];
-    if (grp == 0u) {
-      // hashed: byte offset = base + ((hx ^ hy ^ hz) & mask) << shift, with the
-      // mask and shift folded into the per-axis terms
-      const uint32_t m = F.Tmask << kShift;
-      const uint32_t hx0 = (i0[0] * P.mx) << kShift, hx1 = hx0 + (P.mx << kShift);
-      const uint32_t hy0 = (i0[1] * P.my) << kShift, hy1 = hy0 + (P.my << kShift);
-      const uint32_t hz0 = (i0[2] * P.mz) << kShift, hz1 = hz0 + (P.mz << kShift);
-      const uint32_t x0 = hx0 & m, x1 = hx1 & m, y0 = hy0 & m, y1 = hy1 & m, z0 = hz0 & m, z1 = hz1 & m;
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        off[c] = base + (((c & 1) ? x1 : x0) ^ ((c & 2) ? y1 : y0) ^ ((c & 4) ? z1 : z0));
-    } else {
-      const uint32_t ax0 = i0[0] * P.mx, ax1 = ax0 + P.mx;
-      const uint32_t ay0 = i0[1] * P.my, ay1 = ay0 + P.my;
-      const uint32_t az0 = i0[2] * P.mz, az1 = az0 + P.mz;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const uint32_t a = (c & 1) ? ax1 : ax0, b = (c & 2) ? ay1 : ay0, e = (c & 4) ? az1 : az0;
-        const uint32_t idx = (grp == 0xFu || P.dense) ? (a + b + e) : ((a ^ b ^ e) & F.Tmask);
-        off[c] = base + (idx << kShift);
-      }
-    }
+    corner_offsets(F, P, (F.dense_mask >> (4 * j)) & 0xFu, i0, off);
     float v0[8], v1[8];
     if (TAB16) {
       uint32_t raw[8];
@@ -486,6 +491,53 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     }
     feat[2 * j] = w * acc0;
     feat[2 * j + 1] = w * acc1;
+    ++fetches;
+  }
+}
+
+// FP16-table encode for the 16-bit MLP paths: same addresses and gathers as
+// encode_point, but the trilinear interpolation runs as seven packed FP16
+// lerps over both features at once (fractions and LOD weight rounded to
+// FP16), and the result stays packed: hfeat[j] = (f0, f1) of level g + 4j,
+// the layout the FP16 MFMA operand takes.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ half2_t h2_splat(float v) {
+  return __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(v, v));
+}
+__device__ __forceinline__ half2_t h2_lerp(half2_t a, half2_t b, half2_t f) {
+  return __builtin_elementwise_fma(f, b - a, a);
+}
+
+__device__ __forceinline__ void encode_point_h2(const FieldDev& F, const LevelDev* lv, __amdgpu_buffer_rsrc_t tab,
+                                                const float x[3], float lstar, bool active, int g,
+                                                uint32_t hfeat[4], uint32_t& fetches) {
+  float uh[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) uh[a] = x[a] - F.amin[a];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    hfeat[j] = 0u;
+    const int lev = g + 4 * j;
+    if (!active || lev >= (int)F.L) continue;
+    const float w = F.lod ? __builtin_amdgcn_fmed3f(lstar + 1.0f - (float)lev, 0.0f, 1.0f) : 1.0f;
+    if (!(w > 0.0f)) continue;
+    const LevelDev P = lv[lev];
+    float fr[3];
+    uint32_t i0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) i0[a] = base_corner_fast(uh[a], P.s_hi, P.below_n, fr[a]);
+    uint32_t off[8];
+    corner_offsets(F, P, (F.dense_mask >> (4 * j)) & 0xFu, i0, off);
+    half2_t v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      v[c] = __builtin_bit_cast(half2_t, __builtin_amdgcn_raw_buffer_load_b32(tab, (int)off[c], 0, 0));
+    const half2_t fx = h2_splat(fr[0]), fy = h2_splat(fr[1]), fz = h2_splat(fr[2]);
+    const half2_t e00 = h2_lerp(v[0], v[1], fx), e10 = h2_lerp(v[2], v[3], fx);
+    const half2_t e01 = h2_lerp(v[4], v[5], fx), e11 = h2_lerp(v[6], v[7], fx);
+    const half2_t e0 = h2_lerp(e00, e10, fy), e1 = h2_lerp(e01, e11, fy);
+    hfeat[j] = __builtin_bit_cast(uint32_t, h2_lerp(e0, e1, fz) * h2_splat(w));
     ++fetches;
   }
 }
@@ -599,10 +651,11 @@ __device__ __forceinline__ v4f bias_acc(const float* sb, int base, int g) {
   return r;
 }
 
+// ReLU as one median-of-three (fmaxf would also canonicalise its input)
 __device__ __forceinline__ v4f relu4(v4f v) {
   v4f r;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) r[i] = fmaxf(v[i], 0.0f);
+  for (int i = 0; i < 4; ++i) r[i] = __builtin_amdgcn_fmed3f(v[i], 0.0f, 3.0e38f);
   return r;
 }
 
@@ -688,31 +741,44 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
 }
 
 // 16-bit paths: v_mfma_f32_16x16x32_{f16,bf16}; 8 k-values per lane per step.
-__device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
 template <bool BF>
 struct Half8 {
   typedef typename std::conditional<BF, v8bf, v8h>::type vec;
+  // eight FP32 values rounded to the element type (nearest even)
   __device__ static __forceinline__ vec pack(const float* v) {
     vec r;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      if constexpr (BF) {
-        const uint16_t b = bf16_bits_rne(v[i]);
-        __bf16 x;
-        __builtin_memcpy(&x, &b, 2);
-        r[i] = x;
-      } else {
-        r[i] = (_Float16)v[i];
-      }
+      if constexpr (BF) r[i] = (__bf16)v[i];
+      else r[i] = (_Float16)v[i];
     }
     return r;
   }
+  // ReLU of eight FP32 values, rounded to the element type.  Rounding is
+  // monotone and maps 0 to 0, so relu(round(x)) = round(relu(x)); the FP16
+  // form rounds first and takes the maximum two lanes at a time.
+  __device__ static __forceinline__ vec relu_pack(const float* v) {
+    if constexpr (BF) {
+      float c[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_fmed3f(v[i], 0.0f, 3.0e38f);
+      return pack(c);
+    } else {
+      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+      const h2 zero = {(_Float16)0.0f, (_Float16)0.0f};
+      uint32_t w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const h2 h = {(_Float16)v[2 * i], (_Float16)v[2 * i + 1]};
+        w[i] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(h, zero));
+      }
+      vec r;
+      __builtin_memcpy(&r, w, 16);
+      return r;
+    }
+  }
   __device__ static __forceinline__ uint16_t bits(float f) {
-    if constexpr (BF) return bf16_bits_rne(f);
+    if constexpr (BF) return __builtin_bit_cast(uint16_t, (__bf16)f);
     else return __builtin_bit_cast(uint16_t, (_Float16)f);
   }
   // four values rounded to the element type, packed two per 32-bit word
@@ -754,10 +820,10 @@ __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const 
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(h[ot][r], 0.0f);
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = h[ot][r];
   v4f o = zero4();
-  o = H::mfma(wfrag(kW16_D2, 0), H::pack(hv), o);
-  o = H::mfma(wfrag(kW16_D2, 1), H::pack(hv + 8), o);
+  o = H::mfma(wfrag(kW16_D2, 0), H::relu_pack(hv), o);
+  o = H::mfma(wfrag(kW16_D2, 1), H::relu_pack(hv + 8), o);
   o = add_bias4(o, sb, kB2, g);
   const float oo[4] = {o[0], o[1], o[2], o[3]};
   const vec cv = H::pack4_raw(oo, shh);
@@ -767,8 +833,8 @@ __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const 
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(c1[ot][r], 0.0f);
-  const vec a0 = H::pack(hv), a1 = H::pack(hv + 8);
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = c1[ot][r];
+  const vec a0 = H::relu_pack(hv), a1 = H::relu_pack(hv + 8);
   v4f c2[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) {
@@ -780,10 +846,10 @@ __device__ __forceinline__ void mlp_tile_16(const uint4* __restrict__ sw, const 
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = fmaxf(c2[ot][r], 0.0f);
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = c2[ot][r];
   v4f c3 = zero4();
-  c3 = H::mfma(wfrag(kW16_C3, 0), H::pack(hv), c3);
-  c3 = H::mfma(wfrag(kW16_C3, 1), H::pack(hv + 8), c3);
+  c3 = H::mfma(wfrag(kW16_C3, 0), H::relu_pack(hv), c3);
+  c3 = H::mfma(wfrag(kW16_C3, 1), H::relu_pack(hv + 8), c3);
   c3 = add_bias4(c3, sb, kB5, g);
   o0 = o[0];
   lg[0] = c3[0];
@@ -818,9 +884,8 @@ __device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const
         if (t < nt) {
           const v4f a = H::mfma(w0, in[t], bias_acc(sb, boff + 32 * pair, g));
           const v4f b = H::mfma(w1, in[t], bias_acc(sb, boff + 32 * pair + 16, g));
-          const float hv[8] = {fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f),
-                               fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f)};
-          out[t][pair] = H::pack(hv);
+          const float hv[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+          out[t][pair] = H::relu_pack(hv);
         }
     }
   };
@@ -852,9 +917,8 @@ __device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const
       if (t < nt) {
         const v4f a = H::mfma(wa1, c1p[t][1], H::mfma(wa0, c1p[t][0], bias_acc(sb, kB4 + 32 * pair, g)));
         const v4f b = H::mfma(wb1, c1p[t][1], H::mfma(wb0, c1p[t][0], bias_acc(sb, kB4 + 32 * pair + 16, g)));
-        const float hv[8] = {fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f),
-                             fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f)};
-        c2p[t][pair] = H::pack(hv);
+        const float hv[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+        c2p[t][pair] = H::relu_pack(hv);
       }
   }
   v4f c3[NB];

@@ -27,11 +27,14 @@ constexpr int kW16Total = 10240;    // 16-bit values
 constexpr int kB1 = 0, kB2 = 64, kB3 = 80, kB4 = 144, kB5 = 208, kBiasTotal = 224;
 
 struct LevelDev {
-  uint32_t N;        // lattice resolution (N + 1 points per axis)
+  float top;         // N - 1: the largest base corner (N + 1 lattice points per axis)
   uint32_t dense;    // 1: index = x + y s + z s^2 with s = N + 1
-  uint32_t mx, my, mz;  // per-axis multipliers: (1, s, s^2) dense, hash primes otherwise
+  uint32_t bx, by, bz;  // per-axis multipliers times the entry size in bytes: (1, s, s^2) dense,
+                        // hash primes otherwise (products taken mod 2^32)
   float s_hi, s_lo;  // N / extent as an unevaluated sum of two floats
-  uint32_t pad;
+  uint32_t base;     // byte offset of the level's table
+  float below_n;     // largest float below N (clamp of the lattice coordinate, 16-bit paths)
+  uint32_t pad[3];
 };
 
 struct FieldDev {
@@ -44,6 +47,7 @@ struct FieldDev {
   const uint16_t* wbf;       // kW16Total bf16 bits
   const float* bias;         // kBiasTotal
   uint32_t L, log2T, Tmask, table_f16;
+  uint32_t bmask;            // Tmask times the entry size in bytes (hash mask on byte offsets)
   uint32_t G, Gb, Gc, cshift, nsh;
   float amin[3], cs;         // cs = fp32(G / extent)
   float dt, t_min, extent, inv_ln_f;

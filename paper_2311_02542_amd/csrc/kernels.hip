@@ -24,7 +24,17 @@ namespace vrn {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-__device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + expf(-z)); }
+// exp for compositing: the FP32 path keeps the library expf; the 16-bit
+// paths, whose inputs carry FP16 rounding already, use the hardware
+// exponential (one multiply and v_exp_f32).
+template <bool FAST>
+__device__ __forceinline__ float comp_exp(float z) {
+  if constexpr (FAST) return __expf(z);
+  else return expf(z);
+}
+
+template <bool FAST>
+__device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + comp_exp<FAST>(-z)); }
 
 template <int MODE>
 struct WeightSmem {
@@ -96,8 +106,12 @@ __device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, ui
   }
 }
 
+#ifndef VRN_WAVES16
+#define VRN_WAVES16 4
+#endif
+
 template <bool TAB16, int MODE, int GEO>
-__global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(RenderArgs A) {
+__global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : VRN_WAVES16) void render_kernel(RenderArgs A) {
   __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
   __shared__ float s_b[kBiasTotal];
   __shared__ LevelDev s_lv[kMaxLevels];
@@ -273,9 +287,17 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
           if (t < cnt) {
             bool act;
             const int src = tile_source(&s_slot[wave_base], ns, t0 + t, lane, act);
-            float feat[8];
-            tile_encode<TAB16, false>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
-            xin[t] = H::pack(feat);
+            if constexpr (TAB16 && MODE == 1) {
+              const float px[3] = {shfl_f(sx[0], src), shfl_f(sx[1], src), shfl_f(sx[2], src)};
+              uint32_t hf[4];
+              encode_point_h2(F, s_lv, tab, px, shfl_f(slst, src), act, lane >> 4, hf, st_fetch);
+              const uint4 u = make_uint4(hf[0], hf[1], hf[2], hf[3]);
+              __builtin_memcpy(&xin[t], &u, 16);
+            } else {
+              float feat[8];
+              tile_encode<TAB16, false>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
+              xin[t] = H::pack(feat);
+            }
             shh[t] = s_sh[(wave_base + src) * 4 + (lane >> 4)];
           }
         float o0[kMlpBatch], lg[kMlpBatch][3];
@@ -298,12 +320,13 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : 4) void render_kernel(Rende
 
     // ---- 4. composite (FP32), terminate --------------------------------
     if (has) {
-      const float sd = expf(so0) * sdt;
-      const float trans = expf(-sd);
+      constexpr bool kFast = MODE != 0;
+      const float sd = comp_exp<kFast>(so0) * sdt;
+      const float trans = comp_exp<kFast>(-sd);
       const float wgt = T * (1.0f - trans);
-      cr = fmaf(wgt, sigmoidf(sl0), cr);
-      cg = fmaf(wgt, sigmoidf(sl1), cg);
-      cb = fmaf(wgt, sigmoidf(sl2), cb);
+      cr = fmaf(wgt, sigmoidf<kFast>(sl0), cr);
+      cg = fmaf(wgt, sigmoidf<kFast>(sl1), cg);
+      cb = fmaf(wgt, sigmoidf<kFast>(sl2), cb);
       T = T * trans;
       ++n;
       ++st_samples;
@@ -428,9 +451,9 @@ __global__ __launch_bounds__(kBlock) void mlp_kernel(FieldDev F, const float* fe
   run_mlp<MODE>(s_w, s_b, F, f, shs, lane, o0, lg);
   if (act && g == 0) {
     sigma[p] = expf(o0);
-    rgb[3 * p] = sigmoidf(lg[0]);
-    rgb[3 * p + 1] = sigmoidf(lg[1]);
-    rgb[3 * p + 2] = sigmoidf(lg[2]);
+    rgb[3 * p] = sigmoidf<false>(lg[0]);
+    rgb[3 * p + 1] = sigmoidf<false>(lg[1]);
+    rgb[3 * p + 2] = sigmoidf<false>(lg[2]);
   }
 }
 
