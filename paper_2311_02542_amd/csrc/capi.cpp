@@ -368,6 +368,26 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
       coarse[ci >> 5] |= 1u << (ci & 31);
     }
   }
+  // the coarse grid dilated by one block: empty only where the block and all
+  // 26 neighbours are empty (long empty runs are walked block by block)
+  std::vector<uint32_t> coarse_dil(coarse.size(), 0u);
+  for (uint32_t cz = 0; cz < Gc; ++cz)
+    for (uint32_t cy = 0; cy < Gc; ++cy)
+      for (uint32_t cx = 0; cx < Gc; ++cx) {
+        bool any = false;
+        for (int dz = -1; dz <= 1 && !any; ++dz)
+          for (int dy = -1; dy <= 1 && !any; ++dy)
+            for (int dx = -1; dx <= 1 && !any; ++dx) {
+              const int x = (int)cx + dx, y = (int)cy + dy, z = (int)cz + dz;
+              if (x < 0 || y < 0 || z < 0 || x >= (int)Gc || y >= (int)Gc || z >= (int)Gc) continue;
+              const uint64_t ci = (uint64_t)x + (uint64_t)Gc * ((uint64_t)y + (uint64_t)Gc * (uint64_t)z);
+              any = (coarse[ci >> 5] >> (ci & 31)) & 1u;
+            }
+        if (any) {
+          const uint64_t ci = (uint64_t)cx + (uint64_t)Gc * ((uint64_t)cy + (uint64_t)Gc * (uint64_t)cz);
+          coarse_dil[ci >> 5] |= 1u << (ci & 31);
+        }
+      }
   std::vector<float> w32, bias;
   std::vector<uint16_t> w16, wbf;
   arrange_weights(d->weights, (int)L, (int)nsh, w32, w16, wbf, bias);
@@ -402,7 +422,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
     }
   }
   const uint64_t tab_bytes = n_tab * (d->table_dtype == VRN_F16 ? 2 : 4);
-  const uint64_t need = tab_bytes + bricks.size() * 8 + coarse.size() * 4 + (w32.size() + bias.size()) * 4 +
+  const uint64_t need = tab_bytes + bricks.size() * 8 + coarse.size() * 8 + (w32.size() + bias.size()) * 4 +
                         (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev);
   if (ctx->budget && ctx->used + need > ctx->budget)
     return fail(VRN_ERR_BUDGET, "loading the field would exceed the HBM budget");
@@ -414,12 +434,13 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   uint8_t* tab = nullptr;
   LevelDev* dlv = nullptr;
   unsigned long long* dbr = nullptr;
-  uint32_t* dco = nullptr;
+  uint32_t *dco = nullptr, *dcd = nullptr;
   float *dw32 = nullptr, *dbias = nullptr, *dlat = nullptr;
   uint16_t *dw16 = nullptr, *dwbf = nullptr;
   if ((e = upload(f, static_cast<const uint8_t*>(d->tables), tab_bytes, &tab)) ||
       (e = upload(f, lv.data(), lv.size(), &dlv)) || (e = upload(f, bricks.data(), bricks.size(), &dbr)) ||
-      (e = upload(f, coarse.data(), coarse.size(), &dco)) || (e = upload(f, w32.data(), w32.size(), &dw32)) ||
+      (e = upload(f, coarse.data(), coarse.size(), &dco)) ||
+      (e = upload(f, coarse_dil.data(), coarse_dil.size(), &dcd)) || (e = upload(f, w32.data(), w32.size(), &dw32)) ||
       (e = upload(f, w16.data(), w16.size(), &dw16)) || (e = upload(f, wbf.data(), wbf.size(), &dwbf)) ||
       (e = upload(f, bias.data(), bias.size(), &dbias)) ||
       (use_table && (e = upload(f, lat.data(), lat.size(), &dlat)))) {
@@ -431,6 +452,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.levels = dlv;
   F.bricks = dbr;
   F.coarse = dco;
+  F.coarse_dil = dcd;
   F.w32 = dw32;
   F.w16 = dw16;
   F.wbf = dwbf;

@@ -283,12 +283,59 @@ __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float 
   return false;
 }
 
+// Walk the coarse grid from block (bx, by, bz) along the ray through
+// consecutive blocks whose dilated bit is clear (the block and its 26
+// neighbours hold no occupied cell) and return the ray parameter where the
+// walk leaves the last such block (the next block is not clear, or the grid
+// ends).  Every point within one block width of a clear block lies in an
+// empty block.  The walk and the canonical sample positions both deviate
+// from the exact ray by far less than a block, so every lattice sample with
+// t up to the returned value (rounded either way) has an empty cell.
+__device__ __forceinline__ float coarse_run(const FieldDev& F, const uint32_t* dil, const Ray& r, int bx, int by,
+                                            int bz) {
+  const float cb = (float)(1u << F.cshift);
+  const int Gc = (int)F.Gc;
+  const float dq[3] = {r.dx * F.cs, r.dy * F.cs, r.dz * F.cs};
+  const float qo[3] = {(r.ox - F.amin[0]) * F.cs, (r.oy - F.amin[1]) * F.cs, (r.oz - F.amin[2]) * F.cs};
+  const int b0[3] = {bx, by, bz};
+  float tm[3], td[3];
+  int st[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float inv = __builtin_amdgcn_rcpf(dq[a]);
+    st[a] = dq[a] > 0.0f ? 1 : (dq[a] < 0.0f ? -1 : 0);
+    tm[a] = st[a] == 0 ? 3.0e38f : ((float)(b0[a] + (st[a] > 0)) * cb - qo[a]) * inv;
+    td[a] = st[a] == 0 ? 3.0e38f : cb * fabsf(inv);
+  }
+  int x = bx, y = by, z = bz;
+  float tx = tm[0], ty = tm[1], tz = tm[2];
+  float t_exit = 0.0f;
+  for (int it = 0; it < 3 * Gc; ++it) {
+    const bool ax = tx <= ty && tx <= tz;
+    const bool ay = !ax && ty <= tz;
+    const bool az = !ax && !ay;
+    t_exit = ax ? tx : (ay ? ty : tz);
+    x += ax ? st[0] : 0;
+    y += ay ? st[1] : 0;
+    z += az ? st[2] : 0;
+    if ((unsigned)x >= (unsigned)Gc || (unsigned)y >= (unsigned)Gc || (unsigned)z >= (unsigned)Gc) break;
+    if (bit_set(dil, (uint32_t)x + (uint32_t)Gc * ((uint32_t)y + (uint32_t)Gc * (uint32_t)z))) break;
+    tx += ax ? td[0] : 0.0f;
+    ty += ay ? td[1] : 0.0f;
+    tz += az ? td[2] : 0.0f;
+  }
+  return t_exit;
+}
+
 // Advance to the next evaluated sample within `budget` lattice tests.
 // Returns 1 (sample found; st, sx are its canonical t and x), 0 (budget used
 // up) or 2 (ray exhausted).  Occupancy is tested hierarchically: the coarse
 // grid (blocks of 2^cshift cells, in LDS), then the 4x4x4 brick (one 64-bit
 // load, kept in registers while the ray stays in the brick), then the cell
-// bit.  Empty coarse blocks and empty bricks are skipped with skip_box.
+// bit.  On the uniform lattice, a sample in a clear block (dilated bit 0)
+// jumps to the end of the run of clear blocks (coarse_run); other empty
+// coarse blocks and empty bricks are skipped with skip_box.  `coarse` holds
+// the coarse grid and, kCoarseWords later, its dilation.
 template <int GEO>
 __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coarse, Ray& r, uint32_t budget,
                                           uint32_t& steps, float& st, float sx[3]) {
@@ -305,7 +352,19 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
     float bsize = 0.0f;
     if ((unsigned)cx < (unsigned)G && (unsigned)cy < (unsigned)G && (unsigned)cz < (unsigned)G) {
       const int bx = cx >> F.cshift, by = cy >> F.cshift, bz = cz >> F.cshift;
-      if (!bit_set(coarse, (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz))) {
+      const uint32_t ci = (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz);
+      if (!bit_set(coarse, ci)) {
+        if constexpr (GEO == 0) {
+          // a clear block starts a run of empty blocks: jump to its end
+          if (!bit_set(coarse + kCoarseWords, ci)) {
+            const float te = coarse_run(F, coarse + kCoarseWords, r, bx, by, bz);
+            const int kb = (int)fminf(floorf(te * F.inv_dt - 0.5f), (float)r.k_hi);
+            if (kb > r.k) {
+              r.k = kb + 1;
+              continue;
+            }
+          }
+        }
         bo[0] = bx;
         bo[1] = by;
         bo[2] = bz;

@@ -42,6 +42,8 @@ struct FieldDev {
   const LevelDev* levels;    // [L]
   const unsigned long long* bricks;  // Gb^3 bricks of 4x4x4 cells, bit (x&3) + 4 (y&3) + 16 (z&3)
   const uint32_t* coarse;    // Gc^3 bits (Gc <= 32), block = 2^cshift cells; staged in LDS
+  const uint32_t* coarse_dil;  // Gc^3 bits: 1 if the block or one of its 26 neighbours has an
+                               // occupied cell; staged in LDS after the coarse grid
   const float* w32;          // kW32Total
   const uint16_t* w16;       // kW16Total fp16 bits
   const uint16_t* wbf;       // kW16Total bf16 bits

@@ -67,10 +67,14 @@ __device__ __forceinline__ void run_mlp(const uint8_t* s_w, const float* s_b, co
                            o0, lg);
 }
 
-// Stage the coarse occupancy grid into LDS.
+// Stage the coarse occupancy grid and its dilation into LDS ([kCoarseWords]
+// words each).
 __device__ __forceinline__ void load_coarse(const FieldDev& F, uint32_t* s_coarse) {
   const uint32_t words = (F.Gc * F.Gc * F.Gc + 31u) / 32u;
-  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) s_coarse[i] = F.coarse[i];
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) {
+    s_coarse[i] = F.coarse[i];
+    s_coarse[kCoarseWords + i] = F.coarse_dil[i];
+  }
 }
 
 // The lane that owns compacted sample s = 16 t + (lane & 15), from the
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : VRN_WAVES16) void render_ke
   __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
   __shared__ float s_b[kBiasTotal];
   __shared__ LevelDev s_lv[kMaxLevels];
-  __shared__ uint32_t s_coarse[kCoarseWords];
+  __shared__ uint32_t s_coarse[2 * kCoarseWords];
   __shared__ uint32_t s_off[kMaxCams + 1];
   __shared__ uint32_t s_rb[kMaxCams], s_re[kMaxCams];
   __shared__ uint32_t s_stats[6];
@@ -383,7 +387,7 @@ __global__ void rays_kernel(const vrn_camera* cams, uint32_t n_cams, uint32_t W,
 template <int GEO>
 __global__ void march_kernel(FieldDev F, const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H,
                              uint32_t* klist, uint32_t max_k, uint32_t* count) {
-  __shared__ uint32_t s_coarse[kCoarseWords];
+  __shared__ uint32_t s_coarse[2 * kCoarseWords];
   load_coarse(F, s_coarse);
   __syncthreads();
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -582,6 +586,27 @@ __global__ void coarse_from_bricks_kernel(FieldDev F, uint32_t* coarse) {
   coarse[word] = out;
 }
 
+__global__ void dilate_coarse_kernel(FieldDev F, uint32_t* dil) {
+  const uint32_t word = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t Gc = F.Gc, nc = Gc * Gc * Gc;
+  if (word >= (nc + 31) / 32) return;
+  uint32_t out = 0u;
+  for (uint32_t j = 0; j < 32; ++j) {
+    const uint32_t c = word * 32 + j;
+    if (c >= nc) break;
+    const int cx = (int)(c % Gc), cy = (int)((c / Gc) % Gc), cz = (int)(c / (Gc * Gc));
+    bool any = false;
+    for (int k = 0; k < 27 && !any; ++k) {
+      const int x = cx + k % 3 - 1, y = cy + (k / 3) % 3 - 1, z = cz + k / 9 - 1;
+      if (x < 0 || y < 0 || z < 0 || x >= (int)Gc || y >= (int)Gc || z >= (int)Gc) continue;
+      const uint32_t i = (uint32_t)x + Gc * ((uint32_t)y + Gc * (uint32_t)z);
+      any = (F.coarse[i >> 5] >> (i & 31u)) & 1u;
+    }
+    if (any) out |= 1u << j;
+  }
+  dil[word] = out;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -662,6 +687,8 @@ hipError_t launch_set_occupancy(const FieldDev& F, const uint32_t* bits, hipStre
   const uint32_t words = (F.Gc * F.Gc * F.Gc + 31) / 32;
   hipLaunchKernelGGL(coarse_from_bricks_kernel, dim3((words + 255) / 256), dim3(256), 0, s, F,
                      const_cast<uint32_t*>(F.coarse));
+  hipLaunchKernelGGL(dilate_coarse_kernel, dim3((words + 255) / 256), dim3(256), 0, s, F,
+                     const_cast<uint32_t*>(F.coarse_dil));
   return hipGetLastError();
 }
 
