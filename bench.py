@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true", help="skip the PQ error check")
     ap.add_argument("--cpu-crop", type=int, default=256, help="oracle crop side per eye")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="oracle processes (capped by the host CPUs)")
     ap.add_argument("--error-pixels", type=int, default=4096)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain 1 GiB device copy (to scale profiler byte counters)")
@@ -131,18 +132,42 @@ def pq_error(R, fid, field_ref, cams, W, H, compute, n_px, seed=0):
             "psnr_pq": float(10 * math.log10(1.0 / max(mse, 1e-30))), "pixels": int(n_px)}
 
 
-def cpu_baseline(field, cams, W, H, crop):
-    """The FP64 oracle as it stands, single process, on a central crop of each eye."""
-    from oracle.render import all_pixels, render_fp64
-    r0 = (H - crop) // 2
-    c0 = (W - crop) // 2
-    px = all_pixels(len(cams), W, H, rows=np.arange(r0, r0 + crop), cols=np.arange(c0, c0 + crop))
+_ORACLE_FIELD = None
+
+
+def _oracle_chunk(job):
+    """One worker's share: the oracle on a block of pixels of one camera."""
+    from threadpoolctl import threadpool_limits
+    from oracle.render import render_fp64
+    cam, W, H, px = job
+    with threadpool_limits(1):
+        out = render_fp64(_ORACLE_FIELD, [cam], W, H, pixels=px)
+    return int(out["n"].sum()), int(px.shape[0])
+
+
+def cpu_baseline(field, frames, frame_ids, W, H, crop, workers):
+    """The FP64 oracle as it stands on a central crop of both eyes of the given
+    frames, spread over `workers` forked processes (one BLAS thread each).
+    Runs before the GPU is touched, so the fork copies no GPU state."""
+    import multiprocessing
+    from oracle.render import all_pixels
+    global _ORACLE_FIELD
+    _ORACLE_FIELD = field
+    r0, c0 = (H - crop) // 2, (W - crop) // 2
+    crop_px = all_pixels(1, W, H, rows=np.arange(r0, r0 + crop), cols=np.arange(c0, c0 + crop))
+    jobs = [(cam, W, H, crop_px[b:b + 2048]) for f in frame_ids for cam in frames[f]
+            for b in range(0, crop_px.shape[0], 2048)]
     t0 = time.perf_counter()
-    out = render_fp64(field, cams, W, H, pixels=px)
+    with multiprocessing.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_chunk, jobs, chunksize=1)
     dt = time.perf_counter() - t0
-    return {"value": px.shape[0] / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
-            "samples_per_s": float(out["n"].sum() / dt),
-            "sample": f"central {crop}x{crop} crop of both eyes of frame 0 ({px.shape[0]} rays, {dt:.1f} s)"}
+    _ORACLE_FIELD = None
+    samples = sum(r[0] for r in res)
+    rays = sum(r[1] for r in res)
+    return {"value": rays / dt, "unit": "rays/s", "cores": workers, "kind": "oracle",
+            "samples_per_s": samples / dt,
+            "sample": f"central {crop}x{crop} crop of both eyes of frames {', '.join(map(str, frame_ids))} "
+                      f"({rays} rays, {samples} samples, {dt:.1f} s on {workers} processes)"}
 
 
 def main():
@@ -151,14 +176,21 @@ def main():
         print(f"bench.py renders whole frames on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU row sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
-    import torch
-    from paper_2311_02542_amd import capi, synth
+    from paper_2311_02542_amd import synth
 
     W = H = 2048
     field32 = synth.field_c4(table_dtype=np.float32)
     field16 = dict(field32)
     field16["tables"] = field32["tables"].astype(np.float16)
     frames = synth.cameras_c4()
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(field32, frames, (0, 150, 299), W, H, args.cpu_crop,
+                           max(1, min(args.cpu_workers, os.cpu_count() or 1)))
+
+    import torch
+    from paper_2311_02542_amd import capi
     R = capi.Renderer(0)
     paths = [p for p in args.paths.split(",") if p]
     fids = {}
@@ -228,9 +260,8 @@ def main():
         torch.cuda.synchronize()
         line["calib_copy_bytes"] = src.numel() * 4
         del src, dst
-    if not args.no_cpu_baseline:
-        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(field32, frames[0], W, H, args.cpu_crop)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     R.close()
     print(json.dumps(line), flush=True)
 
