@@ -202,3 +202,54 @@ def test_mlp_parity(R, case, compute, tol_rgb, tol_sig):
     c_err = np.abs(rgb.cpu().numpy() - c_ref)
     assert s_err.max() <= tol_sig, f"sigma rel err {s_err.max():.3g}"
     assert c_err.max() <= tol_rgb, f"rgb abs err {c_err.max():.3g}"
+
+
+def test_march_bit_exact_clear_runs(R):
+    """Long runs of clear coarse blocks (the block DDA path): occupied cells sit
+    one cell across block boundaries and rays run along block faces, edges and
+    through block corners, where a walk error would pass an occupied cell."""
+    g = 128                                     # 4-cell coarse blocks, 32^3 of them
+    occ = np.zeros((g, g, g), bool)
+    rng = np.random.default_rng(7)
+    for _ in range(60):                         # isolated cells just across block faces
+        c = rng.integers(1, g // 4 - 1, size=3) * 4 + rng.choice([-1, 0], size=3)
+        occ[c[2], c[1], c[0]] = True
+    occ[:, :, 63] = True                        # a wall one cell before a block face (x = 64)
+    occ[64, 20:100, 20:100] = True              # a slab on a block face (z = 64)
+    f = tiny_field(g, occ, (0.0, 0.0, 0.0), 1.0, cap=4096, seed=3)
+    cell = 1.0 / g
+    cams = []
+    perms = [np.eye(3), np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]), np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]])]
+    for k in range(9):
+        # origins on block faces / edges / corners (multiples of 4 cells), some outside the grid
+        pos = cell * 4 * np.array([1 + (5 * k) % 30, 2 + (7 * k) % 29, 3 + (11 * k) % 28], float)
+        if k % 4 == 3:
+            pos = pos - 0.6
+        cams.append(axis_camera(perms[k % 3], pos, W=24, H=24, fx=6.0 + 2 * k, cx=12.0, cy=12.0))
+    assert _check_march(R, f, cams, 24, 24) > 1000
+
+
+def test_march_and_render_at_maximum_grid(R):
+    """The largest occupancy grid the library accepts (G = 1024; 16-cell coarse
+    blocks, 256^3 bricks) with 16 hashed levels: march bit-exact and the FP32
+    image within 1e-5 PQ on sampled pixels."""
+    from gpu_common import compare_render
+    from oracle.render import render_fp64
+    g = 1024
+    occ = np.zeros((g, g, g), bool)
+    occ[100:110, 200:900, 200:900] = True       # a thick floor-like slab (z)
+    occ[300:700, 500:510, 300:700] = True       # a wall (y)
+    occ[400:420, 400:420, 100:900] = True       # a beam (x)
+    f = tiny_field(g, occ, (-2.0, -2.0, -2.0), 4.0, cap=2048, seed=11, L=16, log2_T=19, lod=True, b_sigma=3.0)
+    f["dt"] = float(F32(4.0 * math.sqrt(3) / 2048))
+    cams = [axis_camera(np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]), [-1.5, 0.3, 0.1], W=16, H=16, fx=9.0,
+                        cx=8.0, cy=8.0),
+            axis_camera(np.eye(3), [0.1, -0.3, -1.9], W=16, H=16, fx=7.0, cx=8.0, cy=8.0)]
+    assert _check_march(R, f, cams, 16, 16) > 500
+    fid = R.load(f)
+    rgba, ns = R.render(fid, cams, 16, 16, "f32")
+    R.torch.cuda.synchronize()
+    R.unload(fid)
+    ref = render_fp64(f, cams, 16, 16)
+    mx, _, _ = compare_render(rgba.cpu().numpy(), ns.cpu().numpy(), ref, 1e-5)
+    assert mx <= 1e-5 and ref["n"].sum() > 100
