@@ -126,6 +126,20 @@ class Server:
             self.pending.append(r)
         return r
 
+    def warmup(self, shapes):
+        """Allocate and capture, on every slot, the buckets of every scene for
+        the given (W, H, n_cams) shapes, so that no capture (and its device
+        synchronisation) happens while requests are being served.  Stops at
+        the HBM budget."""
+        for slot in self.slots:
+            for scene in self.fids:
+                for (W, H, n) in shapes:
+                    key = (scene, W, H, n, self.compute)
+                    if self._used_bytes() + n * W * H * 20 > self.budget:
+                        return
+                    self._admit_bucket(slot, key, n, W, H)
+        self.torch.cuda.synchronize()
+
     def start(self):
         self._stop.clear()
         self._thread = threading.Thread(target=self._loop, daemon=True)
@@ -353,6 +367,10 @@ def main():
                                    "p99_ms": float(np.percentile(lat, 99) * 1e3), "req_per_s": capacity}}
     base.close()
     srv = Server(fields, budget, n_slots=args.slots, compute="f16", use_graphs=True)
+    # graphs for every bucket the mix can produce (single-camera requests
+    # merge up to max_batch cameras; stereo requests carry two)
+    srv.warmup([(256, 256, k) for k in range(1, srv.max_batch + 1)] +
+               [(1024, 1024, k) for k in range(1, srv.max_batch + 1)] + [(2048, 2048, 2)])
     # capacity of the serving path: a saturating burst
     print("serve: saturating burst", file=sys.stderr, flush=True)
     reqs, wall = drive(srv, args.requests, 1e6)
