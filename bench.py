@@ -236,8 +236,11 @@ def main():
         "value": hr["rays_per_s"], "unit": "rays/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f16": "f16 tables + f16 MFMA (fp32 accumulate, fp32 march/composite)",
-                  "bf16": "f16 tables + bf16 MFMA", "f32": "f32"}[head],
+        "dtype": {"f16": "f16", "bf16": "bf16", "f32": "f32"}[head],
+        "dtype_detail": {"f16": "f16 tables, f16 MFMA with f32 accumulate; march, transmittance and "
+                                "compositing in f32",
+                         "bf16": "f16 tables, bf16 MFMA with f32 accumulate; f32 march/composite",
+                         "f32": "f32 tables, f32 MFMA, f32 throughout"}[head],
         "data": "synthetic (seeded walkable 16 m scene, random-init field, 300-frame head path)",
         "config": {"workload": "stereo VR frame: 2x2048x2048, 100 deg FOV, 64 mm IPD, 16 levels x 2^22 x 2, "
                                "512^3 occupancy (3%), LOD on, <=2048 samples/ray, 300-frame walk",
