@@ -783,20 +783,29 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
   }
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) c2[ot] = relu4(add_bias4(c2[ot], sb, kB4 + 16 * ot, g));
-  v4f c3 = zero4();
+  // color output layer (64 -> 3) on the VALU: 13 of the 16 MFMA output rows
+  // would be padding.  Lane (s, g) holds hidden units 16 it + 4 g + r of
+  // sample s; the weights W5[16 it + 4 g + r][c] sit in the C3 fragments of
+  // lanes 16 g + c.  Each lane dots its 16 units, then the four lane groups
+  // of a sample are summed.
+  float p[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const float4 w = sw[kW32_C3 / 4 + it * 64 + lane];
-    c3 = mfma_f32(w.x, c2[it][0], c3);
-    c3 = mfma_f32(w.y, c2[it][1], c3);
-    c3 = mfma_f32(w.z, c2[it][2], c3);
-    c3 = mfma_f32(w.w, c2[it][3], c3);
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4 w = sw[kW32_C3 / 4 + it * 64 + 16 * g + c];
+      p[c] = fmaf(w.x, c2[it][0], p[c]);
+      p[c] = fmaf(w.y, c2[it][1], p[c]);
+      p[c] = fmaf(w.z, c2[it][2], p[c]);
+      p[c] = fmaf(w.w, c2[it][3], p[c]);
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    p[c] += __shfl_xor(p[c], 16);
+    p[c] += __shfl_xor(p[c], 32);
+    lg[c] = p[c] + sb[kB5 + c];
   }
-  c3 = add_bias4(c3, sb, kB5, g);
   o0 = o[0];
-  lg[0] = c3[0];
-  lg[1] = c3[1];
-  lg[2] = c3[2];
 }
 
 // 16-bit paths: v_mfma_f32_16x16x32_{f16,bf16}; 8 k-values per lane per step.
