@@ -283,20 +283,19 @@ __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float 
   return false;
 }
 
-// Walk the coarse grid from block (bx, by, bz) along the ray through
+// Walk the coarse grid from block (bx, by, bz) along a straight ray through
 // consecutive blocks whose dilated bit is clear (the block and its 26
-// neighbours hold no occupied cell) and return the ray parameter where the
-// walk leaves the last such block (the next block is not clear, or the grid
-// ends).  Every point within one block width of a clear block lies in an
-// empty block.  The walk and the canonical sample positions both deviate
-// from the exact ray by far less than a block, so every lattice sample with
-// t up to the returned value (rounded either way) has an empty cell.
-__device__ __forceinline__ float coarse_run(const FieldDev& F, const uint32_t* dil, const Ray& r, int bx, int by,
-                                            int bz) {
+// neighbours hold no occupied cell) and lie in [blo, bhi] on every axis,
+// and return the ray parameter where the walk leaves the last such block.
+// The ray in cell units is qo + t dq.  Every point within one block width of
+// a clear block lies in an empty block.  The walk and the canonical sample
+// positions both deviate from the exact ray by far less than a block, so
+// every lattice sample with t up to the returned value (rounded either way)
+// has an empty cell.
+__device__ __forceinline__ float coarse_run(const FieldDev& F, const uint32_t* dil, const float qo[3],
+                                            const float dq[3], int bx, int by, int bz, int blo, int bhi) {
   const float cb = (float)(1u << F.cshift);
   const int Gc = (int)F.Gc;
-  const float dq[3] = {r.dx * F.cs, r.dy * F.cs, r.dz * F.cs};
-  const float qo[3] = {(r.ox - F.amin[0]) * F.cs, (r.oy - F.amin[1]) * F.cs, (r.oz - F.amin[2]) * F.cs};
   const int b0[3] = {bx, by, bz};
   float tm[3], td[3];
   int st[3];
@@ -318,7 +317,7 @@ __device__ __forceinline__ float coarse_run(const FieldDev& F, const uint32_t* d
     x += ax ? st[0] : 0;
     y += ay ? st[1] : 0;
     z += az ? st[2] : 0;
-    if ((unsigned)x >= (unsigned)Gc || (unsigned)y >= (unsigned)Gc || (unsigned)z >= (unsigned)Gc) break;
+    if (x < blo || y < blo || z < blo || x > bhi || y > bhi || z > bhi) break;
     if (bit_set(dil, (uint32_t)x + (uint32_t)Gc * ((uint32_t)y + (uint32_t)Gc * (uint32_t)z))) break;
     tx += ax ? td[0] : 0.0f;
     ty += ay ? td[1] : 0.0f;
@@ -327,15 +326,101 @@ __device__ __forceinline__ float coarse_run(const FieldDev& F, const uint32_t* d
   return t_exit;
 }
 
+// Contracted fields, outside the unit L-inf ball: the canonical samples lie
+// on the image of the straight ray under C.  Over a stretch [t_a, t_b] on
+// which one axis i dominates u at both ends, with the same sign and
+// |u_i| > 1, it dominates throughout (|u_j| - |u_i| is convex in t and
+// |u_i| linear), so y_i = sign (2 - 1/|u_i|) is monotone, and y_j = a b with
+// a = 2 - 1/|u_i| in (1, 2) and b = u_j / |u_i| both monotone: the products
+// of their end values bound y_j.  When every coarse block touched by that
+// box (padded by a hundredth of a cell) is clear, every sample of the
+// stretch, whose canonical position is within FP32 error of the curve, has
+// an empty cell.  A doubling search returns the farthest lattice index
+// r.k + 2^j whose stretch from r.k passes (r.k itself when none does).
+__device__ __forceinline__ int contracted_run(const FieldDev& F, const uint32_t* dil, const Ray& r) {
+  const float g4 = 0.25f * (float)F.G;
+  const float inv_cb = 1.0f / (float)(1u << F.cshift);
+  const int Gc = (int)F.Gc;
+  auto ucoord = [&](float t, float u[3]) {
+    u[0] = (r.ox + t * r.dx - F.center[0]) * F.inv_radius;
+    u[1] = (r.oy + t * r.dy - F.center[1]) * F.inv_radius;
+    u[2] = (r.oz + t * r.dz - F.center[2]) * F.inv_radius;
+  };
+  auto dominant = [](const float u[3], int& axis, float& m) {
+    const float ax = fabsf(u[0]), ay = fabsf(u[1]), az = fabsf(u[2]);
+    axis = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    m = fmaxf(ax, fmaxf(ay, az));
+  };
+  float ua[3];
+  ucoord(F.lat[r.k], ua);
+  int ia;
+  float ma;
+  dominant(ua, ia, ma);
+  const float sa = ia == 0 ? ua[0] : (ia == 1 ? ua[1] : ua[2]);
+  if (!(ma > 1.0f)) return r.k;
+  const float aa = 2.0f - 1.0f / ma;
+  // does the stretch [r.k, kb] stay in clear blocks?
+  auto stretch_clear = [&](int kb) -> bool {
+    float ub[3];
+    ucoord(F.lat[kb], ub);
+    int ib;
+    float mb;
+    dominant(ub, ib, mb);
+    const float sb = ib == 0 ? ub[0] : (ib == 1 ? ub[1] : ub[2]);
+    if (ib != ia || (sa > 0.0f) != (sb > 0.0f) || !(mb > 1.0f)) return false;
+    const float ab = 2.0f - 1.0f / mb;
+    const float alo = fminf(aa, ab), ahi = fmaxf(aa, ab);
+    int b0[3], b1[3];
+    bool fits = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float lo, hi;
+      if (a == ia) {
+        lo = sa > 0.0f ? alo : -ahi;
+        hi = sa > 0.0f ? ahi : -alo;
+      } else {
+        const float ba = ua[a] / ma, bb = ub[a] / mb;
+        const float blo = fminf(ba, bb), bhi = fmaxf(ba, bb);
+        lo = fminf(fminf(alo * blo, alo * bhi), fminf(ahi * blo, ahi * bhi));
+        hi = fmaxf(fmaxf(alo * blo, alo * bhi), fmaxf(ahi * blo, ahi * bhi));
+      }
+      b0[a] = (int)floorf(((lo + 2.0f) * g4 - 0.01f) * inv_cb);
+      b1[a] = (int)floorf(((hi + 2.0f) * g4 + 0.01f) * inv_cb);
+      fits = fits && b0[a] >= 0 && b1[a] < Gc && b1[a] - b0[a] <= 1;
+    }
+    if (!fits) return false;
+    bool clear = true;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int x = b0[0] + (c & 1), y = b0[1] + ((c >> 1) & 1), z = b0[2] + (c >> 2);
+      if (x <= b1[0] && y <= b1[1] && z <= b1[2])
+        clear = clear && !bit_set(dil, (uint32_t)x + (uint32_t)Gc * ((uint32_t)y + (uint32_t)Gc * (uint32_t)z));
+    }
+    return clear;
+  };
+  // gallop: double the stretch while it stays clear (a finer search past the
+  // first failure costs more probes than it saves lattice tests)
+  int best = r.k;
+  for (int step = 1; step < (1 << 20); step *= 2) {
+    const int kb = min(r.k + step, r.k_hi);
+    if (kb <= best || !stretch_clear(kb)) break;
+    best = kb;
+    if (kb == r.k_hi) break;
+  }
+  return best;
+}
+
 // Advance to the next evaluated sample within `budget` lattice tests.
 // Returns 1 (sample found; st, sx are its canonical t and x), 0 (budget used
 // up) or 2 (ray exhausted).  Occupancy is tested hierarchically: the coarse
 // grid (blocks of 2^cshift cells, in LDS), then the 4x4x4 brick (one 64-bit
 // load, kept in registers while the ray stays in the brick), then the cell
-// bit.  On the uniform lattice, a sample in a clear block (dilated bit 0)
-// jumps to the end of the run of clear blocks (coarse_run); other empty
-// coarse blocks and empty bricks are skipped with skip_box.  `coarse` holds
-// the coarse grid and, kCoarseWords later, its dilation.
+// bit.  A sample in a clear block (dilated bit 0) jumps to the end of the
+// run of clear blocks: along the straight ray for bounded fields and inside
+// the unit ball of contracted ones (coarse_run), along bounds of the curved
+// image beyond it (contracted_run).  Other empty coarse blocks and empty
+// bricks are skipped with skip_box.  `coarse` holds the coarse grid and,
+// kCoarseWords later, its dilation.
 template <int GEO>
 __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coarse, Ray& r, uint32_t budget,
                                           uint32_t& steps, float& st, float sx[3]) {
@@ -354,15 +439,47 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
       const int bx = cx >> F.cshift, by = cy >> F.cshift, bz = cz >> F.cshift;
       const uint32_t ci = (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz);
       if (!bit_set(coarse, ci)) {
-        if constexpr (GEO == 0) {
+        if (!bit_set(coarse + kCoarseWords, ci)) {
           // a clear block starts a run of empty blocks: jump to its end
-          if (!bit_set(coarse + kCoarseWords, ci)) {
-            const float te = coarse_run(F, coarse + kCoarseWords, r, bx, by, bz);
-            const int kb = (int)fminf(floorf(te * F.inv_dt - 0.5f), (float)r.k_hi);
-            if (kb > r.k) {
-              r.k = kb + 1;
-              continue;
-            }
+          int kb = r.k;
+          // straight walks: bounded fields, and blocks wholly inside the unit
+          // ball of contracted ones (q in [G/4, 3G/4], where C is the
+          // identity); beyond it the curved image of the ray is bounded
+          // piecewise (contracted_run)
+          float qo[3], dq[3];
+          int blo = 0, bhi = (int)F.Gc - 1;
+          bool walk = true;
+          if (GEO == 1 && F.contract) {
+            const int ilo = (int)(F.G >> (2 + F.cshift)), ihi = (int)((3 * F.G) >> (2 + F.cshift)) - 1;
+            walk = bx >= ilo && by >= ilo && bz >= ilo && bx <= ihi && by <= ihi && bz <= ihi &&
+                   (ilo << F.cshift) == (int)(F.G >> 2) && ((ihi + 1) << F.cshift) == (int)((3 * F.G) >> 2);
+            blo = ilo;
+            bhi = ihi;
+            const float s = F.inv_radius * 0.25f * (float)F.G;
+            qo[0] = (r.ox - F.center[0]) * s + 0.5f * (float)F.G;
+            qo[1] = (r.oy - F.center[1]) * s + 0.5f * (float)F.G;
+            qo[2] = (r.oz - F.center[2]) * s + 0.5f * (float)F.G;
+            dq[0] = r.dx * s;
+            dq[1] = r.dy * s;
+            dq[2] = r.dz * s;
+          } else {
+            qo[0] = (r.ox - F.amin[0]) * F.cs;
+            qo[1] = (r.oy - F.amin[1]) * F.cs;
+            qo[2] = (r.oz - F.amin[2]) * F.cs;
+            dq[0] = r.dx * F.cs;
+            dq[1] = r.dy * F.cs;
+            dq[2] = r.dz * F.cs;
+          }
+          if (walk) {
+            const float te = coarse_run(F, coarse + kCoarseWords, qo, dq, bx, by, bz, blo, bhi);
+            if constexpr (GEO == 0) kb = (int)fminf(floorf(te * F.inv_dt - 0.5f), (float)r.k_hi);
+            else kb = min(table_count_le(F, te) - 1, r.k_hi);
+          } else if (GEO == 1 && F.contract) {
+            kb = contracted_run(F, coarse + kCoarseWords, r);
+          }
+          if (kb > r.k) {
+            r.k = kb + 1;
+            continue;
           }
         }
         bo[0] = bx;
