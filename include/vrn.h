@@ -4,7 +4,7 @@
  * SIGGRAPH Asia 2023, arXiv 2311.02542).
  *
  * The library renders an instant-NGP-style radiance field ray by ray:
- *   occupancy-bitfield lattice march (Sec. 4.3, "binary occupancy grid"),
+ *   occupancy-bitfield lattice march (Sec. 4.3, binary occupancy grid),
  *   multiresolution hash encoding with LOD mip-mapping (Sec. 4.2.1, Eq. 3;
  *   dense coarse levels and skipped fine levels, App. D),
  *   density MLP (1 hidden layer of 64) and color MLP (2 hidden layers of 64,
@@ -225,8 +225,8 @@ vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const 
 
 /* ---- occupancy maintenance ---- */
 
-/* Grid-based occupancy pruning (Sec. 4.3 "Joint history- and grid-based
- * pruning"; App. C: 4 evenly placed points per voxel).  For every occupied
+/* Grid-based occupancy pruning (Sec. 4.3, the grid half of its joint
+ * pruning; App. C: 4 evenly placed points per voxel).  For every occupied
  * voxel of the resident field, the density MLP (all hash levels, no LOD) is
  * evaluated at points_per_voxel points -- 4: the alternating corners of the
  * voxel's 2x2x2 sub-lattice at offsets {1/4, 3/4}; 1, 8, 27, 64: a p^3 grid
@@ -239,7 +239,7 @@ vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_
                           vrn_dtype compute, uint32_t* d_bits_out, float* d_max_opacity, void* hip_stream);
 
 /* Replace a resident field's occupancy with device bits (same layout as
- * vrn_field_desc.occ_bits), rebuilding its bricks and coarse grid on
+ * vrn_field_desc.occ_bits), rebuilding its bricks and coarse grids on
  * hip_stream.  Renders of this field on other streams must be ordered by
  * the caller. */
 vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* hip_stream);

@@ -10,7 +10,7 @@
 * LOD (Sec. 4.2.1): sample footprint r_hat = t * r; optimal level
   L* = -log_f(2 s r_hat) in the normalised [0,1]^3 coordinates, plus the LOD
   bias (Sec. 4.2.2); per-level weights w_l of Eq. 3; levels with w_l = 0
-  are never read (App. D, "replace the finest levels with zeros").
+  are never read (App. D: the finest levels are zeroed rather than fetched).
   Reading: L* is clamped at 0 so level 0 always has weight 1.
 
 Positions: x_n = (x - aabb_min) / extent in FP64 from the canonical FP32

@@ -1,5 +1,5 @@
-"""Grid-based occupancy pruning, FP64 -- Sec. 4.3 ("Joint history- and
-grid-based pruning") and App. C ("Ablation on pruning strategy").
+"""Grid-based occupancy pruning, FP64 -- Sec. 4.3 (the grid half of the
+joint history and grid pruning) and App. C (the pruning ablation).
 
 Grid pruning estimates the maximum density inside each occupancy voxel by
 evaluating the density MLP on points placed evenly inside it (the paper uses
