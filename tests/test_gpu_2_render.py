@@ -166,3 +166,32 @@ def test_srgb_display_output(R, ev):
     err = np.abs(got[ok, :3] - want[ok]).max()
     assert err <= 2e-5, err
     np.testing.assert_allclose(got[:, 3], ref["rgba"][:, 3], atol=1e-5)
+
+
+def test_maximum_cameras_and_table_size(R):
+    """The largest accepted configuration of the hash grid (16 levels, T = 2^24,
+    FP16: 1 GiB of tables) rendered through VRN_MAX_CAMS = 16 cameras in one
+    call: FP32 MLP within 1e-5 and bit-exact counts against the oracle on
+    sampled pixels, and the FP16 path within the precision budget."""
+    occ = np.zeros((64, 64, 64), bool)
+    occ[20:44, 20:44, 30:34] = True
+    occ[10:54, 40:42, 10:54] = True
+    f = tiny_field(64, occ, cap=512, seed=21, L=16, log2_T=24, lod=True, table_dtype=np.float16, b_sigma=3.0)
+    cams = [axis_camera(np.eye(3) if c % 2 == 0 else np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]),
+                        [0.3 + 0.02 * c, 0.45, -0.6] if c % 2 == 0 else [-0.6, 0.35 + 0.02 * c, 0.5],
+                        W=40, H=32, fx=30.0, cx=20.0, cy=16.0) for c in range(capi.MAX_CAMS)]
+    fid = R.load(f)
+    rgba, ns = R.render(fid, cams, 40, 32, "f32")
+    h16, _ = R.render(fid, cams, 40, 32, "f16")
+    R.torch.cuda.synchronize()
+    R.unload(fid)
+    rng = np.random.default_rng(4)
+    px = np.stack([rng.integers(0, capi.MAX_CAMS, 400), rng.integers(0, 32, 400), rng.integers(0, 40, 400)], 1)
+    ref = render_fp64(f, cams, 40, 32, pixels=px)
+    sel = (px[:, 0] * 32 + px[:, 1]) * 40 + px[:, 2]
+    g = rgba.cpu().numpy().reshape(-1, 4)[sel]
+    n = ns.cpu().numpy().reshape(-1)[sel]
+    mx, _, _ = compare_render(g, n, ref, TOL)
+    assert mx <= TOL and ref["n"].sum() > 200
+    e16 = np.abs(h16.cpu().numpy().reshape(-1, 4)[sel][:, :3] - ref["rgba"][:, :3])
+    assert e16.max() <= 1 / 1023 and e16.mean() <= 1 / 4095
