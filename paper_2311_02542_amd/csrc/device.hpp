@@ -30,18 +30,6 @@ __device__ __forceinline__ int shfl_i(int v, int src) {
   return __builtin_amdgcn_ds_bpermute(src << 2, v);
 }
 
-// Position of the n-th (0-based) set bit of m; n < popcount(m).
-__device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
-  int pos = 0;
-#pragma unroll
-  for (int w = 32; w >= 1; w >>= 1) {
-    const uint64_t low = m & ((w == 64 ? 0ull : (1ull << w)) - 1ull);
-    const int c = __popcll(low);
-    if (n >= c) { n -= c; m >>= w; pos += w; } else { m = low; }
-  }
-  return pos;
-}
-
 // ---------------------------------------------------------------------------
 // Rays (Sec. 4.2.1 cone footprint; pinhole, OpenCV axes, pixel centres +0.5)
 // ---------------------------------------------------------------------------

@@ -110,6 +110,9 @@ __device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, ui
   }
 }
 
+// Waves per SIMD the 16-bit kernels are compiled for (register budget
+// 512 / waves).  4 measured fastest on the stereo C4 frame; 3 would let two
+// tiles share each weight read but loses the latency cover of a fourth wave.
 #ifndef VRN_WAVES16
 #define VRN_WAVES16 4
 #endif
