@@ -272,7 +272,8 @@ vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t 
   a.budget = (opts && opts->march_budget) ? opts->march_budget : 256u;
   const int compute = opts ? (int)opts->compute : 0;
   const uint64_t rays = (uint64_t)n_cams * W * H;
-  const uint64_t want = (rays + kBlock - 1) / kBlock;
+  const uint64_t bt = (uint64_t)render_block_threads(compute);
+  const uint64_t want = (rays + bt - 1) / bt;
   const uint64_t cap = (uint64_t)ctx->n_cu * render_blocks_per_cu(f->dev, compute);
   const int grid = (int)std::max<uint64_t>(1, std::min(want, cap));
   hipError_t e = launch_render(a, compute, grid, s);

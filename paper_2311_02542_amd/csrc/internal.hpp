@@ -13,6 +13,11 @@ constexpr int kMaxCams = VRN_MAX_CAMS;
 constexpr int kQueues = 8;          // one ray queue per XCD
 constexpr int kTile = 8;            // rays are issued in 8x8 pixel tiles
 constexpr int kBlock = 256;         // threads per render block (4 waves)
+// The FP32-MLP render kernel runs blocks of 8 waves: its 40 KiB of weights in
+// LDS are then shared by twice the waves, so LDS no longer caps it below the
+// 4 waves/SIMD its registers allow.
+constexpr int kBlockF32 = 512;
+inline int render_block_threads(int compute) { return compute == 0 ? kBlockF32 : kBlock; }
 constexpr int kHidden = 64;
 constexpr int kCoarseWords = 1024;  // <= 32^3 bits of coarse occupancy in LDS
 constexpr int kMlpBatch = 1;        // 16-sample tiles per 16-bit MLP call (weights read once per call)

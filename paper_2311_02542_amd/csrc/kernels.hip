@@ -118,7 +118,9 @@ __device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, ui
 #endif
 
 template <bool TAB16, int MODE, int GEO>
-__global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : VRN_WAVES16) void render_kernel(RenderArgs A) {
+__global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN_WAVES16) void render_kernel(
+    RenderArgs A) {
+  constexpr int kThreads = MODE == 0 ? kBlockF32 : kBlock;
   __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
   __shared__ float s_b[kBiasTotal];
   __shared__ LevelDev s_lv[kMaxLevels];
@@ -126,8 +128,8 @@ __global__ __launch_bounds__(kBlock, MODE == 0 ? 3 : VRN_WAVES16) void render_ke
   __shared__ uint32_t s_off[kMaxCams + 1];
   __shared__ uint32_t s_rb[kMaxCams], s_re[kMaxCams];
   __shared__ uint32_t s_stats[6];
-  __shared__ uint2 s_sh[MODE == 0 ? 1 : kBlock * 4];
-  __shared__ uint32_t s_slot[kBlock];
+  __shared__ uint2 s_sh[MODE == 0 ? 1 : kThreads * 4];
+  __shared__ uint32_t s_slot[kThreads];
 
   const FieldDev& F = A.F;
   const __amdgpu_buffer_rsrc_t tab = table_rsrc(F);
@@ -619,7 +621,8 @@ static int blocks_per_cu_impl() {
   static int cached = -1;
   if (cached < 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, render_kernel<TAB16, MODE, GEO>, kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, render_kernel<TAB16, MODE, GEO>,
+                                                     render_block_threads(MODE), 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
@@ -658,7 +661,7 @@ static void launch_render_geo(const RenderArgs& a, int compute, dim3 gr, dim3 bl
 }
 
 hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t s) {
-  const dim3 gr(grid), bl(kBlock);
+  const dim3 gr(grid), bl(render_block_threads(compute));
   if (a.F.lat) launch_render_geo<1>(a, compute, gr, bl, s);
   else launch_render_geo<0>(a, compute, gr, bl, s);
   return hipGetLastError();
