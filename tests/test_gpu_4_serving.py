@@ -136,3 +136,29 @@ def test_unload_busy_field_and_errors():
         capi.vrn_render(R.ctx, 999, cams, 2048, 2048, rgba, None)
     assert ei.value.status == capi.VRN_ERR_NOT_FOUND
     R.close()
+
+
+def test_warmup_captures_buckets_and_serves_exactly():
+    """Graphs captured ahead of serving (every slot, scene and shape) replay
+    requests bit-for-bit like a direct render, with no new bucket created."""
+    torch = need_gpu()
+    srv = serve.Server(_fields(), 4 << 30, n_slots=2, compute="f16", use_graphs=True)
+    shapes = [(256, 256, 1), (256, 256, 2)]
+    srv.warmup(shapes)
+    keys = {k for s in srv.slots for k in s.buckets}
+    assert keys == {(sc, w, h, n, "f16") for sc in ("A", "B") for (w, h, n) in shapes}
+    srv.start()
+    reqs = [srv.submit(sc, *synth.request_cameras(sc, "preview", 50 + i)) for i, sc in enumerate("ABAB")]
+    srv.stop(drain=True)
+    assert {k for s in srv.slots for k in s.buckets} == keys
+    R = capi.Renderer(0)
+    fids = {name: R.load(f) for name, f in _fields().items()}
+    for r in reqs:
+        assert r.error is None and r.done.is_set()
+        ref, ref_n = R.render(fids[r.scene], r.cams, r.W, r.H, "f16")
+        torch.cuda.synchronize()
+        assert torch.equal(ref, r.result[0]) and torch.equal(ref_n, r.result[1])
+    for fid in fids.values():
+        R.unload(fid)
+    R.close()
+    srv.close()
