@@ -195,3 +195,46 @@ def test_maximum_cameras_and_table_size(R):
     assert mx <= TOL and ref["n"].sum() > 200
     e16 = np.abs(h16.cpu().numpy().reshape(-1, 4)[sel][:, :3] - ref["rgba"][:, :3])
     assert e16.max() <= 1 / 1023 and e16.mean() <= 1 / 4095
+
+
+@pytest.mark.parametrize("variant", ["sh1_L5", "sh3_bias", "radius_tmin", "f16tables_f32mlp", "f32tables_bf16mlp",
+                                     "nonzero_biases"])
+def test_field_parameter_variants(R, variant):
+    """Field parameters the configs leave at one value: SH bands 1 and 3, an
+    odd level count, LOD bias and radius scale, a loose t_min, nonzero hidden
+    biases, and the mixed table/MLP precisions.  FP32-MLP renders within 1e-5
+    PQ with bit-exact counts; 16-bit MLPs within the precision budget."""
+    rng = np.random.default_rng(77)
+    g = 32
+    occ = rng.uniform(size=(g, g, g)) < 0.08
+    occ[10:22, 10:22, 14:16] = True
+    kw = dict(cap=128, seed=5, L=8, log2_T=12, lod=True, bands=2, table_dtype=np.float32, b_sigma=3.0)
+    compute = "f32"
+    if variant == "sh1_L5":
+        kw.update(L=5, bands=1)
+    elif variant == "sh3_bias":
+        kw.update(bands=3)
+    elif variant == "f16tables_f32mlp":
+        kw.update(table_dtype=np.float16)
+    elif variant == "f32tables_bf16mlp":
+        compute = "bf16"
+    f = tiny_field(g, occ, (-0.5, -0.5, -0.5), 1.0, **kw)
+    if variant == "sh3_bias":
+        f["lod_bias"] = float(F32(-0.7))
+    elif variant == "radius_tmin":
+        f["lod_radius_scale"], f["lod_bias"], f["t_min"] = float(F32(0.5)), float(F32(1.3)), float(F32(1e-2))
+    elif variant == "nonzero_biases":
+        for k in ("b1", "b3", "b4", "b5"):
+            f["mlp"][k] = rng.uniform(-0.2, 0.2, f["mlp"][k].shape).astype(np.float32)
+    cams = [axis_camera(np.eye(3), [0.02, -0.03, -1.2], W=40, H=36, fx=36.0, cx=20.0, cy=18.0),
+            axis_camera(np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]), [-1.1, 0.05, 0.1], W=40, H=36, fx=30.0,
+                        cx=20.0, cy=18.0)]
+    rgba, ns = gpu_render(R, f, cams, 40, 36, compute)
+    ref = render_fp64(f, cams, 40, 36)
+    assert ref["n"].sum() > 500
+    if compute == "f32":
+        mx, _, _ = compare_render(rgba, ns, ref, TOL)
+        assert mx <= TOL
+    else:
+        e = np.abs(rgba.reshape(-1, 4)[:, :3].astype(np.float64) - ref["rgba"][:, :3])
+        assert e.mean() <= 1 / 4095 and e.max() < 0.05
