@@ -150,7 +150,9 @@ const char* vrn_last_error(void);
  * MFMA in FP32, FP16 and BF16).  The field stays resident until unloaded. */
 vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* desc, vrn_field_id* out);
 
-/* Free a field.  VRN_ERR_BUSY while renders that use it are still running. */
+/* Free a field.  VRN_ERR_BUSY while renders that use it are still running.
+ * Renders enqueued under HIP graph capture are not tracked: the caller keeps
+ * the field loaded while a graph that renders it can still be replayed. */
 vrn_status vrn_unload_field(vrn_ctx* ctx, vrn_field_id field);
 
 /* Device bytes held by a resident field. */
@@ -195,7 +197,9 @@ vrn_status vrn_check_cameras(const vrn_camera* cams, uint32_t n_cams, uint32_t W
 vrn_status vrn_read_stats(vrn_ctx* ctx, const void* d_workspace, vrn_stats* out, void* hip_stream);
 
 /* ---- stage entry points: the same device code as vrn_render, one stage at
- *      a time, for parity tests and profiling ---- */
+ *      a time, for parity tests and profiling.  vrn_rays and vrn_march copy
+ *      their cameras into the context's own workspace, so they must not
+ *      overlap on the device with renders that use it. ---- */
 
 /* Canonical FP32 rays of every pixel of every camera, pixel order
  * (cam, row, col): d_o, d_d device [n][3] float, d_r device [n] float cone

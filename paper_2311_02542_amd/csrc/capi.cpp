@@ -424,7 +424,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   }
   const uint64_t tab_bytes = n_tab * (d->table_dtype == VRN_F16 ? 2 : 4);
   const uint64_t need = tab_bytes + bricks.size() * 8 + coarse.size() * 8 + (w32.size() + bias.size()) * 4 +
-                        (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev);
+                        (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev) + lat.size() * 4;
   if (ctx->budget && ctx->used + need > ctx->budget)
     return fail(VRN_ERR_BUDGET, "loading the field would exceed the HBM budget");
 

@@ -728,8 +728,8 @@ hipError_t launch_march(const FieldDev& F, const vrn_camera* d_cams, uint32_t n_
 
 hipError_t launch_encode(const FieldDev& F, const float* xyz, const float* t, const float* r, uint32_t n,
                          float* feat, hipStream_t s) {
-  const uint32_t per_block = (kBlock / 64) * 16;
-  const dim3 gr((n + per_block - 1) / per_block), bl(kBlock);
+  const uint64_t per_block = (kBlock / 64) * 16;
+  const dim3 gr((unsigned)(((uint64_t)n + per_block - 1) / per_block)), bl(kBlock);
   if (F.table_f16) hipLaunchKernelGGL((encode_kernel<true>), gr, bl, 0, s, F, xyz, t, r, n, feat);
   else hipLaunchKernelGGL((encode_kernel<false>), gr, bl, 0, s, F, xyz, t, r, n, feat);
   return hipGetLastError();
@@ -737,8 +737,8 @@ hipError_t launch_encode(const FieldDev& F, const float* xyz, const float* t, co
 
 hipError_t launch_mlp(const FieldDev& F, const float* feat, const float* dir, uint32_t n, int compute,
                       float* sigma, float* rgb, hipStream_t s) {
-  const uint32_t per_block = (kBlock / 64) * 16;
-  const dim3 gr((n + per_block - 1) / per_block), bl(kBlock);
+  const uint64_t per_block = (kBlock / 64) * 16;
+  const dim3 gr((unsigned)(((uint64_t)n + per_block - 1) / per_block)), bl(kBlock);
   if (compute == 0) hipLaunchKernelGGL((mlp_kernel<0>), gr, bl, 0, s, F, feat, dir, n, sigma, rgb);
   else if (compute == 1) hipLaunchKernelGGL((mlp_kernel<1>), gr, bl, 0, s, F, feat, dir, n, sigma, rgb);
   else hipLaunchKernelGGL((mlp_kernel<2>), gr, bl, 0, s, F, feat, dir, n, sigma, rgb);

@@ -168,15 +168,24 @@ def test_srgb_display_output(R, ev):
     np.testing.assert_allclose(got[:, 3], ref["rgba"][:, 3], atol=1e-5)
 
 
-def test_maximum_cameras_and_table_size(R):
-    """The largest accepted configuration of the hash grid (16 levels, T = 2^24,
-    FP16: 1 GiB of tables) rendered through VRN_MAX_CAMS = 16 cameras in one
-    call: FP32 MLP within 1e-5 and bit-exact counts against the oracle on
-    sampled pixels, and the FP16 path within the precision budget."""
+@pytest.mark.parametrize("table_dtype", [np.float16, np.float32])
+def test_maximum_cameras_and_table_size(R, table_dtype):
+    """The largest accepted configuration of the hash grid (16 levels, T = 2^24:
+    1 GiB of FP16 tables, or 2^31 bytes of FP32 tables, where byte offsets
+    and the buffer size reach the top of 32 bits) rendered through
+    VRN_MAX_CAMS = 16 cameras in one call: FP32 MLP within 1e-5 and
+    bit-exact counts against the oracle on sampled pixels, and the FP16 path
+    within the precision budget."""
     occ = np.zeros((64, 64, 64), bool)
     occ[20:44, 20:44, 30:34] = True
     occ[10:54, 40:42, 10:54] = True
-    f = tiny_field(64, occ, cap=512, seed=21, L=16, log2_T=24, lod=True, table_dtype=np.float16, b_sigma=3.0)
+    # FP32 tables render with LOD off, so every sample reads all 16 levels and
+    # the finest ones, hashed over the whole of T, reach byte offsets up to
+    # 2^31 - 8
+    f32_tables = table_dtype == np.float32
+    f = tiny_field(64, occ, cap=512, seed=21, L=16, log2_T=24, lod=not f32_tables, table_dtype=table_dtype,
+                   b_sigma=3.0)
+    assert f["tables"].nbytes == (1 << 30) * np.dtype(table_dtype).itemsize // 2
     cams = [axis_camera(np.eye(3) if c % 2 == 0 else np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]),
                         [0.3 + 0.02 * c, 0.45, -0.6] if c % 2 == 0 else [-0.6, 0.35 + 0.02 * c, 0.5],
                         W=40, H=32, fx=30.0, cx=20.0, cy=16.0) for c in range(capi.MAX_CAMS)]
