@@ -247,3 +247,35 @@ def test_field_parameter_variants(R, variant):
     else:
         e = np.abs(rgba.reshape(-1, 4)[:, :3].astype(np.float64) - ref["rgba"][:, :3])
         assert e.mean() <= 1 / 4095 and e.max() < 0.05
+
+
+@pytest.mark.parametrize("case", ["c2", "unbounded", "c1_exponential"])
+def test_march_budget_does_not_change_the_image(R, case):
+    """The per-round march budget only decides how many lattice tests a ray
+    makes before the wave's next encode/MLP round: it regroups samples into
+    tiles but changes no sample, and every MFMA column depends on its own
+    sample only.  Budgets 1 (a ray suspends after every lattice test, inside
+    clear runs and bricks) and 7 must give images and counts bit-identical
+    to the default, on the uniform lattice and on both sample-table
+    lattices, in FP32 and FP16."""
+    if case == "c2":
+        f, cams, W, H = synth.field_c2(), synth.cameras_c2(1, 128, 128), 128, 128
+    elif case == "unbounded":
+        f, cams, W, H = synth.field_unbounded(), synth.cameras_unbounded(2, 96, 64), 96, 64
+    else:
+        f, cams, W, H = synth.field_c1(), synth.cameras_c1(3), 64, 64
+        f["step_growth"], f["max_lattice"] = float(np.float32(1 / 32)), 300
+    fid = R.load(f)
+    try:
+        for compute in ("f32", "f16"):
+            outs = []
+            for budget in (0, 1, 7):
+                rgba, ns = R.render(fid, cams, W, H, compute, march_budget=budget)
+                R.torch.cuda.synchronize()
+                outs.append((rgba.cpu().numpy(), ns.cpu().numpy()))
+            assert outs[0][1].sum() > 100
+            for rgba, ns in outs[1:]:
+                assert np.array_equal(ns, outs[0][1])
+                assert np.array_equal(rgba, outs[0][0])
+    finally:
+        R.unload(fid)
