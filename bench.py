@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--cpu-crop", type=int, default=256, help="oracle crop side per eye")
     ap.add_argument("--cpu-workers", type=int, default=16, help="oracle processes (capped by the host CPUs)")
     ap.add_argument("--error-pixels", type=int, default=4096)
+    ap.add_argument("--shares", type=int, default=8,
+                    help="also time the head path as N equal row shares of the frame, one share at a time "
+                         "(the work of each of N GPUs under a static row split); 0 = off")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain 1 GiB device copy (to scale profiler byte counters)")
     return ap.parse_args()
@@ -114,6 +117,24 @@ def time_path(R, fid, frames, W, H, compute, steps, warmup):
     lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
     d = {k: s1[k] - s0[k] for k in s1}
     return {"wall_s": wall, "lat_ms": lat, "stats": d, "rgba": rgba, "ns": ns}
+
+
+def time_shares(R, fid, frames, W, H, compute, n, steps, warmup):
+    """The frame as n equal bands of rows (both eyes), each rendered alone
+    through the cameras' row_begin/row_end: what each of n GPUs would render
+    under a static row split.  The spread of the bands' times is the
+    imbalance that the paper's dynamic split removes."""
+    out = []
+    for i in range(n):
+        rb, re = H * i // n, H * (i + 1) // n
+        share = [[dict(c, row_begin=rb, row_end=re) for c in f] for f in frames]
+        r = time_path(R, fid, share, W, H, compute, steps, warmup)
+        ms = float(np.mean(r["lat_ms"]))
+        out.append({"rows": [rb, re], "ms": ms, "rays_per_s": 2 * W * (re - rb) / (ms * 1e-3)})
+        del r
+    mean = float(np.mean([s["ms"] for s in out]))
+    return {"n": n, "path": compute, "steps": steps, "bands": out,
+            "max_over_mean_ms": max(s["ms"] for s in out) / mean}
 
 
 def pq_error(R, fid, field_ref, cams, W, H, compute, n_px, seed=0):
@@ -175,6 +196,9 @@ def main():
     if args.gpus != 1:
         print(f"bench.py renders whole frames on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU row sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    if not 0 <= args.shares <= 2048:
+        print("--shares must be 0..2048 (the rows of one eye)", file=sys.stderr)
         sys.exit(2)
     from paper_2311_02542_amd import synth
 
@@ -263,6 +287,10 @@ def main():
         torch.cuda.synchronize()
         line["calib_copy_bytes"] = src.numel() * 4
         del src, dst
+    if args.shares > 0:
+        print(f"bench: {args.shares} row shares of path {head}", file=sys.stderr, flush=True)
+        line["row_shares"] = time_shares(R, fids[head], frames, W, H, head, args.shares,
+                                         min(args.steps, 20), min(args.warmup, 5))
     if cpu is not None:
         line["cpu_baseline"] = cpu
     R.close()
