@@ -185,7 +185,14 @@ def cpu_baseline(field, frames, frame_ids, W, H, crop, workers):
     _ORACLE_FIELD = None
     samples = sum(r[0] for r in res)
     rays = sum(r[1] for r in res)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": rays / dt, "unit": "rays/s", "cores": workers, "kind": "oracle",
+            "host": f"{os.cpu_count()} CPUs visible, {model}",
             "samples_per_s": samples / dt,
             "sample": f"central {crop}x{crop} crop of both eyes of frames {', '.join(map(str, frame_ids))} "
                       f"({rays} rays, {samples} samples, {dt:.1f} s on {workers} processes)"}
