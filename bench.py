@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "render_kernel_c4_stereo.md")
+PROFILE = os.path.join(ROOT, "profiles", "render_kernel_house_stereo_2x2048.md")
 MFMA_PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "f32": 157.3}
 # MLP FLOPs per evaluated sample (unpadded): density 32x64 + 64x16, color 31x64 + 64x64 + 64x3
 MLP_FLOPS_C4 = 2 * (32 * 64 + 64 * 16 + 31 * 64 + 64 * 64 + 64 * 3)
@@ -210,10 +210,10 @@ def main():
     from paper_2311_02542_amd import synth
 
     W = H = 2048
-    field32 = synth.field_c4(table_dtype=np.float32)
+    field32 = synth.field_house512(table_dtype=np.float32)
     field16 = dict(field32)
     field16["tables"] = field32["tables"].astype(np.float16)
-    frames = synth.cameras_c4()
+    frames = synth.cameras_house_stereo()
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)

@@ -322,7 +322,7 @@ def summarize(reqs, wall_s):
 
 
 def drive(server, n, rate_hz, seed=5004):
-    """Submit a Poisson request stream (config-5 mix) in real time and wait."""
+    """Submit a Poisson request stream (the serving mix of sizes and scenes) in real time and wait."""
     from . import synth
     spec = synth.serving_requests(n, rate_hz, seed)
     server.start()
@@ -339,7 +339,7 @@ def drive(server, n, rate_hz, seed=5004):
 
 
 def main():
-    ap = argparse.ArgumentParser(description="config-5 serving benchmark")
+    ap = argparse.ArgumentParser(description="serving benchmark: mixed resolutions and scenes")
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--budget-gb", type=float, default=8.0)
     ap.add_argument("--slots", type=int, default=4)
@@ -347,7 +347,7 @@ def main():
     args = ap.parse_args()
     import torch
     from . import synth
-    fields = synth.fields_c5()
+    fields = synth.fields_serving()
     budget = int(args.budget_gb * (1 << 30))
     # serial FP32 baseline: one request at a time, no overlap, no graphs
     base = Server(fields, budget, n_slots=1, compute="f32", use_graphs=False)

@@ -8,7 +8,8 @@ renderer's arithmetic (no ray marching, encoding, MLP evaluation or
 compositing), so both the HIP renderer and the CPU oracle can consume what
 it produces without sharing any method code.
 
-RNG: ``numpy.random.default_rng(1000 * config + part)`` with part 1 = tables,
+RNG: ``numpy.random.default_rng(1000 * block + part)``, one seed block per
+workload (1 blob field, 2 room, 4 house, 5 serving room) and part 1 = tables,
 2 = MLP weights, 3 = occupancy, 4 = cameras.
 
 A *field* is a plain dict of numpy arrays and scalars:
@@ -36,8 +37,8 @@ MLP_HIDDEN = 64
 GEO_OUT = 16
 
 
-def rng_for(config: int, part: int) -> np.random.Generator:
-    return np.random.default_rng(1000 * config + part)
+def rng_for(block: int, part: int) -> np.random.Generator:
+    return np.random.default_rng(1000 * block + part)
 
 
 # ----------------------------------------------------------------------------
@@ -167,41 +168,41 @@ def _field(**kw) -> dict:
 # the five workloads
 # ----------------------------------------------------------------------------
 
-def field_c1(extent: float = 1.0, table_dtype=np.float32) -> dict:
+def field_blobs64(extent: float = 1.0, table_dtype=np.float32) -> dict:
     """64^2 / 8 levels / T=2^14 / 64^3 blob bitfield (~10 %), unit cube."""
     L, log2_T, s, f = 8, 14, 16.0, 1.5
     dt = np.float32(extent * math.sqrt(3.0) / 64.0)
     g = 64
     occ = blob_occupancy(rng_for(1, 3), g, 8, 0.10)
     return _field(
-        name="c1", n_levels=L, log2_T=log2_T, level_res=level_resolutions(L, s, f),
+        name="blobs64", n_levels=L, log2_T=log2_T, level_res=level_resolutions(L, s, f),
         base_res=s, growth=f, tables=make_tables(rng_for(1, 1), L, log2_T, "uniform", table_dtype),
         mlp=make_mlp(rng_for(1, 2), L, 2, density_bias(1e-4, 4.0, float(dt))), sh_bands=2,
         occ_res=g, occ_bits=pack_bits(occ), aabb_min=[0.0, 0.0, 0.0], extent=extent,
         dt=dt, max_samples=64, t_min=1e-4, lod_enable=0)
 
 
-def field_c2(log2_T: int = 19, table_dtype=np.float32, config: int = 2) -> dict:
+def field_room256(log2_T: int = 19, table_dtype=np.float32, seed_block: int = 2) -> dict:
     """1024^2 / 16 levels / T=2^19 / 256^3 room bitfield (~5 %), LOD on."""
     L, s, nmax = 16, 16.0, 4096.0
     f64 = (nmax / s) ** (1.0 / (L - 1))
     f = float(np.float32(f64))
     g = 256
     dt = np.float32(math.sqrt(3.0) / 1024.0)
-    occ = room_occupancy(rng_for(config, 3), g, 0.05)
+    occ = room_occupancy(rng_for(seed_block, 3), g, 0.05)
     return _field(
-        name="c2" if log2_T == 19 else f"c2_T{log2_T}", n_levels=L, log2_T=log2_T,
+        name="room256" if log2_T == 19 else f"room256_T{log2_T}", n_levels=L, log2_T=log2_T,
         level_res=level_resolutions(L, s, f64), base_res=s, growth=f,
-        tables=make_tables(rng_for(config, 1), L, log2_T, "normal", table_dtype),
-        mlp=make_mlp(rng_for(config, 2), L, 4, density_bias(1e-4, 2.3, float(dt))), sh_bands=4,
+        tables=make_tables(rng_for(seed_block, 1), L, log2_T, "normal", table_dtype),
+        mlp=make_mlp(rng_for(seed_block, 2), L, 4, density_bias(1e-4, 2.3, float(dt))), sh_bands=4,
         occ_res=g, occ_bits=pack_bits(occ), aabb_min=[0.0, 0.0, 0.0], extent=1.0,
         dt=dt, max_samples=1024, t_min=1e-4, lod_enable=1)
 
 
-def field_c3(table_dtype=np.float16) -> dict:
-    """The config-1 field with its AABB scaled to a 3.2 m cube, FP16 tables."""
-    fld = field_c1(extent=3.2, table_dtype=table_dtype)
-    fld["name"] = "c3"
+def field_blobs_3m2(table_dtype=np.float16) -> dict:
+    """The blob field with its AABB scaled to a 3.2 m cube, FP16 tables."""
+    fld = field_blobs64(extent=3.2, table_dtype=table_dtype)
+    fld["name"] = "blobs_3m2"
     return fld
 
 
@@ -269,7 +270,7 @@ def walkable_occupancy(rng, g: int, extent: float, path_xy: np.ndarray,
     return occ
 
 
-def head_path_c4(n_frames: int = 300, extent: float = 16.0):
+def head_path_house(n_frames: int = 300, extent: float = 16.0):
     """300 frames on a 72 Hz timebase: 0.5 m/s walk along the heading, yaw
     rate jitter of +-30 deg/s (smooth, seeded), eye height 1.6 m."""
     rng = rng_for(4, 4)
@@ -287,15 +288,15 @@ def head_path_c4(n_frames: int = 300, extent: float = 16.0):
     return xy, yaw
 
 
-def field_c4(table_dtype=np.float16) -> dict:
+def field_house512(table_dtype=np.float16) -> dict:
     """Stereo VR scene: 16 m cube, 16 levels, T=2^22, 512^3 bitfield (~3 %)."""
     L, log2_T, s, f = 16, 22, 128.0, 1.4
     g, extent = 512, 16.0
     dt = np.float32(extent * math.sqrt(3.0) / 2048.0)
-    xy, _ = head_path_c4(300, extent)
+    xy, _ = head_path_house(300, extent)
     occ = walkable_occupancy(rng_for(4, 3), g, extent, xy, 0.03)
     return _field(
-        name="c4", n_levels=L, log2_T=log2_T, level_res=level_resolutions(L, s, f),
+        name="house512", n_levels=L, log2_T=log2_T, level_res=level_resolutions(L, s, f),
         base_res=s, growth=f, tables=make_tables(rng_for(4, 1), L, log2_T, "normal", table_dtype),
         mlp=make_mlp(rng_for(4, 2), L, 4, density_bias(1e-4, 4.6, float(dt))), sh_bands=4,
         occ_res=g, occ_bits=pack_bits(occ), aabb_min=[0.0, 0.0, 0.0], extent=extent,
@@ -363,9 +364,9 @@ def cameras_unbounded(n=2, W=256, H=256):
     return out
 
 
-def field_c5c() -> dict:
-    """Serving scene C: config-2 architecture with T=2^20 and FP16 tables."""
-    return field_c2(log2_T=20, table_dtype=np.float16, config=5)
+def field_serving_room() -> dict:
+    """Serving scene C: the room field's architecture with T=2^20 and FP16 tables."""
+    return field_room256(log2_T=20, table_dtype=np.float16, seed_block=5)
 
 
 # ----------------------------------------------------------------------------
@@ -401,13 +402,13 @@ def look_rotation(yaw: float, pitch: float = 0.0) -> np.ndarray:
     return np.stack([right, down, fwd], axis=1)
 
 
-def cameras_c1(n: int = 1, W: int = 64, H: int = 64, seed_part: int = 4):
+def cameras_blobs64(n: int = 1, W: int = 64, H: int = 64, seed_part: int = 4):
     rng = rng_for(1, seed_part)
     return [camera(random_rotation(rng), rng.uniform(0.2, 0.8, 3), W, H, 60.0) for _ in range(n)]
 
 
-def cameras_c2(n: int = 1, W: int = 1024, H: int = 1024, config: int = 2):
-    rng = rng_for(config, 4)
+def cameras_room256(n: int = 1, W: int = 1024, H: int = 1024, seed_block: int = 2):
+    rng = rng_for(seed_block, 4)
     cams = []
     for _ in range(n):
         xy = rng.uniform(0.2, 0.8, 2)
@@ -417,7 +418,7 @@ def cameras_c2(n: int = 1, W: int = 1024, H: int = 1024, config: int = 2):
     return cams
 
 
-def cameras_c3(n: int = 32, W: int = 2048, H: int = 2048):
+def cameras_walk_3m2(n: int = 32, W: int = 2048, H: int = 2048):
     """32 poses along a seeded walk, eye height 1.6 m +- 0.05, smooth yaw."""
     rng = rng_for(3, 4)
     yaw0 = rng.uniform(0, 2 * math.pi)
@@ -441,9 +442,9 @@ def stereo_pair(R: np.ndarray, head: np.ndarray, W: int, H: int, fov_deg: float,
     return [camera(R, head - off, W, H, fov_deg), camera(R, head + off, W, H, fov_deg)]
 
 
-def cameras_c4(frames=None, W: int = 2048, H: int = 2048):
+def cameras_house_stereo(frames=None, W: int = 2048, H: int = 2048):
     """Stereo pairs along the 300-frame head path: list of [left, right]."""
-    xy, yaw = head_path_c4(300, 16.0)
+    xy, yaw = head_path_house(300, 16.0)
     frames = range(300) if frames is None else frames
     out = []
     for i in frames:
@@ -453,13 +454,13 @@ def cameras_c4(frames=None, W: int = 2048, H: int = 2048):
     return out
 
 
-def fields_c5():
-    a = field_c1()
-    a["name"] = "c5a"
-    b = field_c3()
-    b["name"] = "c5b"
-    c = field_c5c()
-    c["name"] = "c5c"
+def fields_serving():
+    a = field_blobs64()
+    a["name"] = "serving_blobs64"
+    b = field_blobs_3m2()
+    b["name"] = "serving_blobs_3m2"
+    c = field_serving_room()
+    c["name"] = "serving_room256_T20"
     return {"A": a, "B": b, "C": c}
 
 

@@ -39,7 +39,7 @@ def test_create_without_device_reports_device_error(lib):
 
 
 def _cam(**kw):
-    c = synth.cameras_c1(1)[0]
+    c = synth.cameras_blobs64(1)[0]
     c = dict(c)
     c.update(kw)
     return c
@@ -83,7 +83,7 @@ def _desc_status(lib, field, **over):
 
 
 def test_field_validation(lib):
-    f = synth.field_c1()
+    f = synth.field_blobs64()
     assert _desc_status(lib, f) == capi.VRN_ERR_INVALID_ARG          # valid field, NULL ctx
     assert _desc_status(lib, f, n_feat=4) == capi.VRN_ERR_UNSUPPORTED
     assert _desc_status(lib, f, n_levels=17) == capi.VRN_ERR_UNSUPPORTED
@@ -105,8 +105,8 @@ def test_field_file_round_trip_two_readers(tmp_path):
     """The writer's files are read back identically by the oracle's reader and
     by the product binding's descriptor marshalling."""
     from oracle.field_io import load_field
-    f = synth.field_c1()
-    prefix = str(tmp_path / "c1")
+    f = synth.field_blobs64()
+    prefix = str(tmp_path / "blobs64")
     synth.save_field(prefix, f)
     g = load_field(prefix)
     for k in ("level_res", "hash_primes", "tables", "occ_bits", "aabb_min"):

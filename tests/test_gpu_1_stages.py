@@ -36,14 +36,14 @@ def _rays(R, cams, W, H):
     return o.cpu().numpy(), d.cpu().numpy(), r.cpu().numpy()
 
 
-@pytest.mark.parametrize("case", ["c1", "c2", "c4stereo", "axis"])
+@pytest.mark.parametrize("case", ["blobs64", "room256", "house_stereo", "axis"])
 def test_rays_bit_exact(R, case):
-    if case == "c1":
-        cams, W, H = synth.cameras_c1(4), 64, 64
-    elif case == "c2":
-        cams, W, H = synth.cameras_c2(2, 96, 72), 96, 72
-    elif case == "c4stereo":
-        cams, W, H = synth.cameras_c4([0, 150], 80, 80)[1], 80, 80
+    if case == "blobs64":
+        cams, W, H = synth.cameras_blobs64(4), 64, 64
+    elif case == "room256":
+        cams, W, H = synth.cameras_room256(2, 96, 72), 96, 72
+    elif case == "house_stereo":
+        cams, W, H = synth.cameras_house_stereo([0, 150], 80, 80)[1], 80, 80
     else:
         cams = [axis_camera(np.eye(3), [0.1, 0.2, 0.3]),
                 axis_camera(np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]), [0.5, 0.5, 0.5])]
@@ -87,13 +87,13 @@ def _check_march(R, field, cams, W, H):
     return total
 
 
-def test_march_bit_exact_c1(R):
-    assert _check_march(R, synth.field_c1(), synth.cameras_c1(6), 64, 64) > 1000
+def test_march_bit_exact_blobs64(R):
+    assert _check_march(R, synth.field_blobs64(), synth.cameras_blobs64(6), 64, 64) > 1000
 
 
-def test_march_bit_exact_c2_room(R):
-    f = synth.field_c2()
-    assert _check_march(R, f, synth.cameras_c2(2, 72, 56), 72, 56) > 1000
+def test_march_bit_exact_room256(R):
+    f = synth.field_room256()
+    assert _check_march(R, f, synth.cameras_room256(2, 72, 56), 72, 56) > 1000
 
 
 @pytest.mark.parametrize("g", [1, 2, 3, 4, 8, 33])
@@ -118,11 +118,11 @@ def test_march_bit_exact_tiny_adversarial(R, g):
 def test_march_empty_full_and_cap(R):
     g = 16
     f0 = tiny_field(g, np.zeros((g, g, g), bool))
-    kl, cnt = _march(R, f0, synth.cameras_c1(2, 16, 16), 16, 16, 8)
+    kl, cnt = _march(R, f0, synth.cameras_blobs64(2, 16, 16), 16, 16, 8)
     assert cnt.max() == 0
     f1 = tiny_field(g, np.ones((g, g, g), bool), cap=7)
-    assert _check_march(R, f1, synth.cameras_c1(2, 16, 16), 16, 16) > 0
-    kl, cnt = _march(R, f1, synth.cameras_c1(1, 16, 16), 16, 16, 7)
+    assert _check_march(R, f1, synth.cameras_blobs64(2, 16, 16), 16, 16) > 0
+    kl, cnt = _march(R, f1, synth.cameras_blobs64(1, 16, 16), 16, 16, 7)
     assert cnt.max() == 7
 
 
@@ -143,17 +143,17 @@ def _sample_points(field, cams, W, H, n_max=20000):
     return x, np.concatenate(ts)[:n_max].astype(F32), np.concatenate(rs)[:n_max].astype(F32)
 
 
-@pytest.mark.parametrize("case", ["c1", "c2_lod", "c4_levels_f16", "c4_levels_f32"])
+@pytest.mark.parametrize("case", ["blobs64", "room256_lod", "house_levels_f16", "house_levels_f32"])
 def test_encode_parity(R, case):
     torch = R.torch
-    if case == "c1":
-        f = synth.field_c1()
-        x, t, r = _sample_points(f, synth.cameras_c1(4), 64, 64)
-    elif case == "c2_lod":
-        f = synth.field_c2()
-        x, t, r = _sample_points(f, synth.cameras_c2(2, 64, 64), 64, 64)
+    if case == "blobs64":
+        f = synth.field_blobs64()
+        x, t, r = _sample_points(f, synth.cameras_blobs64(4), 64, 64)
+    elif case == "room256_lod":
+        f = synth.field_room256()
+        x, t, r = _sample_points(f, synth.cameras_room256(2, 64, 64), 64, 64)
     else:
-        # config-4 level resolutions (up to N = 19912 over a 16 m cube) on a smaller table
+        # the house field's level resolutions (up to N = 19912 over a 16 m cube) on a smaller table
         rng = np.random.default_rng(7)
         f = tiny_field(8, np.ones((8, 8, 8), bool), (0, 0, 0), 16.0, L=16, log2_T=16, lod=True,
                        bands=4, table_dtype=np.float16 if case.endswith("f16") else np.float32)
@@ -180,10 +180,10 @@ def test_encode_parity(R, case):
 
 @pytest.mark.parametrize("compute,tol_rgb,tol_sig", [("f32", 1e-6, 2e-6), ("f16", 5e-3, 5e-2),
                                                      ("bf16", 3e-2, 3e-1)])
-@pytest.mark.parametrize("case", ["c1", "c2"])
+@pytest.mark.parametrize("case", ["blobs64", "room256"])
 def test_mlp_parity(R, case, compute, tol_rgb, tol_sig):
     torch = R.torch
-    f = synth.field_c1() if case == "c1" else synth.field_c2()
+    f = synth.field_blobs64() if case == "blobs64" else synth.field_room256()
     L = int(f["n_levels"])
     rng = np.random.default_rng(11)
     n = 4099  # ragged tail of a 16-sample tile

@@ -34,9 +34,9 @@ def gpu_render(R, field, cams, W, H, compute="f32", linear=False, fid=None):
     return rgba.cpu().numpy(), ns.cpu().numpy()
 
 
-def test_c1_whole_images(R):
-    f = synth.field_c1()
-    cams = synth.cameras_c1(6)
+def test_blobs64_whole_images(R):
+    f = synth.field_blobs64()
+    cams = synth.cameras_blobs64(6)
     rgba, ns = gpu_render(R, f, cams, 64, 64)
     ref = render_fp64(f, cams, 64, 64)
     mx, mean, ties = compare_render(rgba, ns, ref, TOL)
@@ -44,9 +44,9 @@ def test_c1_whole_images(R):
     assert mx <= TOL
 
 
-def test_c2_whole_image_ragged(R):
-    f = synth.field_c2()
-    cams = synth.cameras_c2(2, 100, 77)     # 13 x 10 tiles with ragged edges
+def test_room256_whole_image_ragged(R):
+    f = synth.field_room256()
+    cams = synth.cameras_room256(2, 100, 77)     # 13 x 10 tiles with ragged edges
     rgba, ns = gpu_render(R, f, cams, 100, 77)
     ref = render_fp64(f, cams, 100, 77)
     mx, mean, ties = compare_render(rgba, ns, ref, TOL)
@@ -55,9 +55,9 @@ def test_c2_whole_image_ragged(R):
     assert ref["n"].sum() > 5000
 
 
-def test_c2_full_size_sampled(R):
-    f = synth.field_c2()
-    cams = synth.cameras_c2(1)
+def test_room256_full_size_sampled(R):
+    f = synth.field_room256()
+    cams = synth.cameras_room256(1)
     rgba, ns = gpu_render(R, f, cams, 1024, 1024)
     rng = np.random.default_rng(3)
     px = np.stack([np.zeros(1500, int), rng.integers(0, 1024, 1500), rng.integers(0, 1024, 1500)], 1)
@@ -68,9 +68,9 @@ def test_c2_full_size_sampled(R):
     assert mx <= TOL
 
 
-def test_c4_stereo_full_size_sampled_fp32(R):
-    f = synth.field_c4(table_dtype=np.float32)
-    cams = synth.cameras_c4([0])[0]
+def test_house_stereo_full_size_sampled_fp32(R):
+    f = synth.field_house512(table_dtype=np.float32)
+    cams = synth.cameras_house_stereo([0])[0]
     rgba, ns = gpu_render(R, f, cams, 2048, 2048)
     rng = np.random.default_rng(4)
     m = 300
@@ -86,7 +86,7 @@ def test_c4_stereo_full_size_sampled_fp32(R):
 def test_empty_grid_and_camera_outside(R):
     g = 16
     f = tiny_field(g, np.zeros((g, g, g), bool))
-    rgba, ns = gpu_render(R, f, synth.cameras_c1(2, 32, 32), 32, 32)
+    rgba, ns = gpu_render(R, f, synth.cameras_blobs64(2, 32, 32), 32, 32)
     assert np.all(rgba == 0) and np.all(ns == 0)
     f = tiny_field(g, np.ones((g, g, g), bool), cap=32)
     # outside the cube, looking away from it (+z from above the top face)
@@ -103,8 +103,8 @@ def test_empty_grid_and_camera_outside(R):
 
 def test_row_shares_and_several_cameras(R):
     torch = R.torch
-    f = synth.field_c1()
-    base = synth.cameras_c1(3, 48, 40)
+    f = synth.field_blobs64()
+    base = synth.cameras_blobs64(3, 48, 40)
     fid = R.load(f)
     full, full_n = gpu_render(R, f, base, 48, 40, fid=fid)
     shares = [dict(base[0], row_begin=0, row_end=13), dict(base[1], row_begin=13, row_end=40),
@@ -122,8 +122,8 @@ def test_row_shares_and_several_cameras(R):
 
 
 def test_linear_hdr_output(R):
-    f = synth.field_c1()
-    cams = synth.cameras_c1(2)
+    f = synth.field_blobs64()
+    cams = synth.cameras_blobs64(2)
     pq, _ = gpu_render(R, f, cams, 64, 64)
     lin, _ = gpu_render(R, f, cams, 64, 64, linear=True)
     np.testing.assert_allclose(lin[..., :3], pq_to_linear(pq[..., :3].astype(np.float64)), rtol=2e-4, atol=1e-7)
@@ -132,8 +132,8 @@ def test_linear_hdr_output(R):
 
 def test_deterministic_and_workspace_reuse(R):
     torch = R.torch
-    f = synth.field_c2()
-    cams = synth.cameras_c2(1, 256, 256)
+    f = synth.field_room256()
+    cams = synth.cameras_room256(1, 256, 256)
     fid = R.load(f)
     a1, n1 = gpu_render(R, f, cams, 256, 256, fid=fid)
     a2, n2 = gpu_render(R, f, cams, 256, 256, fid=fid)
@@ -153,8 +153,8 @@ def test_deterministic_and_workspace_reuse(R):
 @pytest.mark.parametrize("ev", [-2.0, 0.0, 3.5])
 def test_srgb_display_output(R, ev):
     from oracle.pq import pq_to_display
-    f = synth.field_c1()
-    cams = synth.cameras_c1(3)
+    f = synth.field_blobs64()
+    cams = synth.cameras_blobs64(3)
     fid = R.load(f)
     disp, _ = R.render(fid, cams, 64, 64, "f32", output="srgb", exposure_ev=ev)
     R.torch.cuda.synchronize()
@@ -209,7 +209,7 @@ def test_maximum_cameras_and_table_size(R, table_dtype):
 @pytest.mark.parametrize("variant", ["sh1_L5", "sh3_bias", "radius_tmin", "f16tables_f32mlp", "f32tables_bf16mlp",
                                      "nonzero_biases"])
 def test_field_parameter_variants(R, variant):
-    """Field parameters the configs leave at one value: SH bands 1 and 3, an
+    """Field parameters the benchmark workloads leave at one value: SH bands 1 and 3, an
     odd level count, LOD bias and radius scale, a loose t_min, nonzero hidden
     biases, and the mixed table/MLP precisions.  FP32-MLP renders within 1e-5
     PQ with bit-exact counts; 16-bit MLPs within the precision budget."""
@@ -249,7 +249,7 @@ def test_field_parameter_variants(R, variant):
         assert e.mean() <= 1 / 4095 and e.max() < 0.05
 
 
-@pytest.mark.parametrize("case", ["c2", "unbounded", "c1_exponential"])
+@pytest.mark.parametrize("case", ["room256", "unbounded", "blobs64_exponential"])
 def test_march_budget_does_not_change_the_image(R, case):
     """The per-round march budget only decides how many lattice tests a ray
     makes before the wave's next encode/MLP round: it regroups samples into
@@ -258,12 +258,12 @@ def test_march_budget_does_not_change_the_image(R, case):
     clear runs and bricks) and 7 must give images and counts bit-identical
     to the default, on the uniform lattice and on both sample-table
     lattices, in FP32 and FP16."""
-    if case == "c2":
-        f, cams, W, H = synth.field_c2(), synth.cameras_c2(1, 128, 128), 128, 128
+    if case == "room256":
+        f, cams, W, H = synth.field_room256(), synth.cameras_room256(1, 128, 128), 128, 128
     elif case == "unbounded":
         f, cams, W, H = synth.field_unbounded(), synth.cameras_unbounded(2, 96, 64), 96, 64
     else:
-        f, cams, W, H = synth.field_c1(), synth.cameras_c1(3), 64, 64
+        f, cams, W, H = synth.field_blobs64(), synth.cameras_blobs64(3), 64, 64
         f["step_growth"], f["max_lattice"] = float(np.float32(1 / 32)), 300
     fid = R.load(f)
     try:

@@ -1,6 +1,6 @@
 """Precision path (FP16 hash tables, FP16 / BF16 MLP on MFMA with FP32
 accumulation, FP32 march and compositing): per-image error against the FP64
-oracle and against the FP32 GPU path, on the 3.2 m config-1 field at a
+oracle and against the FP32 GPU path, on the 3.2 m blob field at a
 2048x2048 eye buffer along the seeded walk.  The FP16 path must meet the
 budget fixed in advance -- mean abs <= 1/4095 and max abs <= 1/1023 PQ (one
 10-bit PQ code) -- BF16 is reported with its error."""
@@ -31,11 +31,11 @@ def _err(a, b):
     return float(e.max()), float(e.mean()), 10 * math.log10(1 / max(mse, 1e-30))
 
 
-def test_c3_precision_report(R):
+def test_precision_report_blobs_3m2(R):
     torch = R.torch
-    f32 = synth.field_c3(table_dtype=np.float32)     # the field before FP16 rounding
-    f16 = synth.field_c3()                           # FP16 tables (the config's form)
-    cams = synth.cameras_c3(32)
+    f32 = synth.field_blobs_3m2(table_dtype=np.float32)     # the field before FP16 rounding
+    f16 = synth.field_blobs_3m2()                           # FP16 tables (the workload's form)
+    cams = synth.cameras_walk_3m2(32)
     W = H = 2048
     fid32, fid16 = R.load(f32), R.load(f16)
     poses = [0, 11, 31]
@@ -80,12 +80,12 @@ def test_c3_precision_report(R):
     assert max(x[0] for x in report["bf16_vs_oracle"]) < 0.05
 
 
-def test_c4_precision_sampled(R):
+def test_precision_house_stereo_sampled(R):
     torch = R.torch
-    f32 = synth.field_c4(table_dtype=np.float32)
+    f32 = synth.field_house512(table_dtype=np.float32)
     f16 = dict(f32)
     f16["tables"] = f32["tables"].astype(np.float16)
-    cams = synth.cameras_c4([150])[0]
+    cams = synth.cameras_house_stereo([150])[0]
     fid = R.load(f16)
     rng = np.random.default_rng(9)
     m = 600

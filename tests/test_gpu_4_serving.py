@@ -15,10 +15,10 @@ pytestmark = pytest.mark.gpu
 def test_graph_replay_equals_eager():
     torch = need_gpu()
     R = capi.Renderer(0)
-    f = synth.field_c1()
+    f = synth.field_blobs64()
     fid = R.load(f)
     W = H = 96
-    cams_all = synth.cameras_c1(5, W, H)
+    cams_all = synth.cameras_blobs64(5, W, H)
     stream = torch.cuda.Stream()
     ws = torch.zeros(capi.vrn_workspace_bytes(R.ctx), dtype=torch.uint8, device="cuda")
     capi.vrn_workspace_init(R.ctx, ws, stream=stream)
@@ -47,7 +47,7 @@ def test_graph_replay_equals_eager():
 
 
 def _fields():
-    return {"A": synth.field_c1(), "B": synth.field_c3()}
+    return {"A": synth.field_blobs64(), "B": synth.field_blobs_3m2()}
 
 
 def test_alone_vs_mix_bitwise():
@@ -88,7 +88,7 @@ def test_alone_vs_mix_bitwise():
 
 def test_admission_budget_and_queueing():
     torch = need_gpu()
-    fields = {"A": synth.field_c1()}
+    fields = {"A": synth.field_blobs64()}
     fbytes = synth.field_bytes(fields["A"])
     # budget fits the field, the slot workspaces and ONE 1024^2 output buffer at a time
     budget = fbytes * 2 + (1 << 20) + 1024 * 1024 * 20 + (1 << 20)
@@ -119,9 +119,9 @@ def test_admission_budget_and_queueing():
 def test_unload_busy_field_and_errors():
     torch = need_gpu()
     R = capi.Renderer(0)
-    f = synth.field_c4(table_dtype=np.float16)
+    f = synth.field_house512(table_dtype=np.float16)
     fid = R.load(f)
-    cams = synth.cameras_c4([0])[0]
+    cams = synth.cameras_house_stereo([0])[0]
     rgba = torch.zeros((2, 2048, 2048, 4), device="cuda")
     capi.vrn_render(R.ctx, fid, cams, 2048, 2048, rgba, None, "f32", workspace=R.ws)
     with pytest.raises(capi.VrnError) as ei:

@@ -33,8 +33,8 @@ def _gpu_prune(R, fid, G, alpha, npts, compute="f32"):
 
 
 @pytest.mark.parametrize("alpha,npts", [(0.2, 4), (0.9, 4), (0.5, 8), (0.9, 27)])
-def test_prune_c1_full_grid(R, alpha, npts):
-    f = synth.field_c1()
+def test_prune_blobs64_full_grid(R, alpha, npts):
+    f = synth.field_blobs64()
     fid = R.load(f)
     bits, mx = _gpu_prune(R, fid, 64, alpha, npts)
     R.unload(fid)
@@ -49,8 +49,8 @@ def test_prune_c1_full_grid(R, alpha, npts):
     print(f"alpha {alpha} pts {npts}: kept {o.sum()} of {occ.sum()} occupied voxels, ties {tie.sum()}")
 
 
-def test_prune_c2_sampled(R):
-    f = synth.field_c2()
+def test_prune_room256_sampled(R):
+    f = synth.field_room256()
     G = 256
     fid = R.load(f)
     bits, mx = _gpu_prune(R, fid, G, 0.983, 4)
@@ -68,7 +68,7 @@ def test_prune_c2_sampled(R):
 
 def test_pruned_field_renders_like_oracle(R):
     torch = R.torch
-    f = synth.field_c1()
+    f = synth.field_blobs64()
     fid = R.load(f)
     bits, _ = _gpu_prune(R, fid, 64, 0.9, 4)
     ref_bits, _, tie = grid_prune_fp64(f, 0.9, 4)
@@ -76,7 +76,7 @@ def test_pruned_field_renders_like_oracle(R):
     pruned = dict(f, occ_bits=bits.copy())
     capi.vrn_set_occupancy(R.ctx, fid, torch.from_numpy(bits.view(np.int32)).cuda())
     torch.cuda.synchronize()
-    cams = synth.cameras_c1(4)
+    cams = synth.cameras_blobs64(4)
     rgba, ns = R.render(fid, cams, 64, 64)
     torch.cuda.synchronize()
     ref = render_fp64(pruned, cams, 64, 64)
@@ -95,7 +95,7 @@ def test_pruned_field_renders_like_oracle(R):
 
 def test_prune_argument_errors(R):
     torch = R.torch
-    f = synth.field_c1()
+    f = synth.field_blobs64()
     fid = R.load(f)
     bits = torch.zeros(8192, dtype=torch.int32, device="cuda")
     for kw in (dict(alpha=1.5), dict(alpha=0.1, points_per_voxel=5)):

@@ -22,20 +22,20 @@ def R():
     r.close()
 
 
-def _c1_exponential():
-    f = synth.field_c1()
+def _blobs64_exponential():
+    f = synth.field_blobs64()
     f["step_growth"] = float(np.float32(1 / 32))
     f["max_lattice"] = 300
     return f
 
 
-@pytest.mark.parametrize("case", ["unbounded", "c1_exponential"])
+@pytest.mark.parametrize("case", ["unbounded", "blobs64_exponential"])
 def test_march_bit_exact(R, case):
     torch = R.torch
     if case == "unbounded":
         f, cams, W, H = synth.field_unbounded(), synth.cameras_unbounded(2, 40, 32), 40, 32
     else:
-        f, cams, W, H = _c1_exponential(), synth.cameras_c1(4, 48, 40), 48, 40
+        f, cams, W, H = _blobs64_exponential(), synth.cameras_blobs64(4, 48, 40), 48, 40
     fid = R.load(f)
     n = len(cams) * W * H
     mk = int(f["max_samples"])
@@ -58,12 +58,12 @@ def test_march_bit_exact(R, case):
     assert total > 100
 
 
-@pytest.mark.parametrize("case", ["unbounded", "c1_exponential"])
+@pytest.mark.parametrize("case", ["unbounded", "blobs64_exponential"])
 def test_render_fp32_parity(R, case):
     if case == "unbounded":
         f, cams, W, H = synth.field_unbounded(), synth.cameras_unbounded(2, 64, 48), 64, 48
     else:
-        f, cams, W, H = _c1_exponential(), synth.cameras_c1(4), 64, 64
+        f, cams, W, H = _blobs64_exponential(), synth.cameras_blobs64(4), 64, 64
     fid = R.load(f)
     rgba, ns = R.render(fid, cams, W, H, "f32")
     R.torch.cuda.synchronize()
