@@ -104,6 +104,7 @@ class Server:
         if self.fixed_bytes > self.budget:
             raise ServeError("resident fields and slot workspaces exceed the HBM budget")
         self.pending = collections.deque()
+        self._claimed = 0           # batches taken from `pending` and not yet launched or requeued
         self.lock = threading.Lock()
         self.done_list = []
         self._rid = 0
@@ -149,7 +150,8 @@ class Server:
         if drain:
             while True:
                 with self.lock:
-                    idle = not self.pending and all(s.busy is None for s in self.slots)
+                    idle = (not self.pending and self._claimed == 0
+                            and all(s.busy is None for s in self.slots))
                 if idle:
                     break
                 time.sleep(0.0005)
@@ -265,6 +267,7 @@ class Server:
                     else:
                         keep.append(r)
                 self.pending = keep
+            self._claimed += 1
             return batch
 
     def _requeue(self, batch):
@@ -280,22 +283,28 @@ class Server:
             if free:
                 batch = self._take_batch()
                 if batch is not None:
-                    if self._launch(free[0], batch):
-                        launched = True
-                    elif len(free) == len(self.slots):
-                        # nothing in flight will free memory: shrink to the head
-                        # request, and fail it if even that cannot be admitted
-                        head, rest = batch[0], batch[1:]
-                        self._requeue(rest)
-                        if not self._launch(free[0], [head]):
-                            head.error = ServeError("request does not fit the HBM budget")
-                            head.done.set()
-                            with self.lock:
-                                self.done_list.append(head)
-                        else:
+                    try:
+                        if self._launch(free[0], batch):
                             launched = True
-                    else:
-                        self._requeue(batch)
+                        elif len(free) == len(self.slots):
+                            # nothing in flight will free memory: shrink to the head
+                            # request, and fail it if even that cannot be admitted
+                            head, rest = batch[0], batch[1:]
+                            self._requeue(rest)
+                            if not self._launch(free[0], [head]):
+                                head.error = ServeError("request does not fit the HBM budget")
+                                head.done.set()
+                                with self.lock:
+                                    self.done_list.append(head)
+                            else:
+                                launched = True
+                        else:
+                            self._requeue(batch)
+                    finally:
+                        # the batch is now on a slot (busy), back in `pending` or
+                        # failed: a draining stop() may look again
+                        with self.lock:
+                            self._claimed -= 1
             if not launched:
                 time.sleep(0.00005)
 

@@ -3,6 +3,8 @@ replays with eager work and synchronisation in between), a request gives the
 same result alone and inside a concurrent mix (bitwise: every ray's
 arithmetic is independent of batch composition), HBM-budget admission and
 queueing, and unload of a busy field."""
+import time
+
 import numpy as np
 import pytest
 
@@ -114,6 +116,28 @@ def test_admission_budget_and_queueing():
         capi.vrn_load_field(ctx, fields["A"])
     assert ei.value.status == capi.VRN_ERR_BUDGET
     capi.vrn_destroy(ctx)
+
+
+def test_drain_waits_for_a_batch_being_launched():
+    """stop(drain=True) must not return while the loop holds a batch it has
+    taken from the queue but not yet put on a slot: _launch is slowed down
+    here so that a drain check always falls into that window."""
+    need_gpu()
+    srv = serve.Server({"A": synth.field_blobs64()}, 8 << 30, n_slots=1, compute="f16", use_graphs=False)
+    launch = srv._launch
+
+    def slow_launch(slot, reqs):
+        time.sleep(0.05)
+        return launch(slot, reqs)
+
+    srv._launch = slow_launch
+    srv.start()
+    reqs = [srv.submit("A", *synth.request_cameras("A", "preview", 7 + i)) for i in range(3)]
+    srv.stop(drain=True)
+    try:
+        assert all(r.done.is_set() and r.error is None for r in reqs)
+    finally:
+        srv.close()
 
 
 def test_unload_busy_field_and_errors():
