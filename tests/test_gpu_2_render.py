@@ -279,3 +279,35 @@ def test_march_budget_does_not_change_the_image(R, case):
                 assert np.array_equal(rgba, outs[0][0])
     finally:
         R.unload(fid)
+
+
+@pytest.mark.parametrize("W,H", [(16384, 12), (12, 16384)])
+def test_maximum_width_and_height(R, W, H):
+    """The widest and tallest accepted frames (16384 pixels): 2048 tiles per
+    tile row, or 2048 tile rows, each with a ragged 12-pixel edge.  Every
+    pixel is rendered (sample counts bit-exact against the oracle on sampled
+    pixels, none left unwritten) and FP32 colors are within 1e-5 PQ."""
+    f = synth.field_blobs64()
+    long_side = max(W, H)
+    # looking into the unit cube from outside, the long side spanning ~90 deg
+    cam = axis_camera(np.eye(3), [0.5, 0.5, -0.6], W=W, H=H, fx=long_side / 2.0, cx=W / 2.0, cy=H / 2.0)
+    rgba = R.torch.full((1, H, W, 4), -1.0, device="cuda")
+    ns = R.torch.full((1, H, W), -1, dtype=R.torch.int32, device="cuda")
+    fid = R.load(f)
+    R.render(fid, [cam], W, H, "f32", out=(rgba, ns))
+    R.torch.cuda.synchronize()
+    R.unload(fid)
+    g = rgba.cpu().numpy().reshape(-1, 4)
+    n = ns.cpu().numpy().reshape(-1)
+    assert (n >= 0).all() and (g[:, 3] >= 0).all()      # every pixel written
+    rng = np.random.default_rng(11)
+    m = 500
+    rows, cols = rng.integers(0, H, m), rng.integers(0, W, m)
+    # the ragged edge and the far corner are always among the samples
+    rows[:4] = [H - 1, H - 1, 0, H - 1]
+    cols[:4] = [W - 1, 0, W - 1, W // 2]
+    px = np.stack([np.zeros(m, np.int64), rows, cols], 1)
+    ref = render_fp64(f, [cam], W, H, pixels=px)
+    sel = rows * W + cols
+    mx, _, _ = compare_render(g[sel], n[sel], ref, TOL)
+    assert mx <= TOL and ref["n"].sum() > 100
