@@ -311,3 +311,38 @@ def test_maximum_width_and_height(R, W, H):
     sel = rows * W + cols
     mx, _, _ = compare_render(g[sel], n[sel], ref, TOL)
     assert mx <= TOL and ref["n"].sum() > 100
+
+
+def test_maximum_pixels_in_one_call(R):
+    """The largest accepted call: 16 cameras of 16384 x 8192 = 2^31 pixels,
+    so pixel indices reach the top of 31 bits and the RGBA output is 32 GiB.
+    Every pixel is written; sampled pixels (the last one included) match the
+    oracle bit-exactly in their sample counts and within 1e-5 PQ in FP32."""
+    torch = R.torch
+    W, H = 16384, 8192
+    f = synth.field_blobs64()
+    cams = [axis_camera(np.eye(3), [0.35 + 0.02 * c, 0.5, -0.6], W=W, H=H, fx=W / 2.0, cx=W / 2.0, cy=H / 2.0)
+            for c in range(capi.MAX_CAMS)]
+    assert capi.MAX_CAMS * W * H == 1 << 31
+    rgba = torch.full((capi.MAX_CAMS, H, W, 4), -1.0, device="cuda")
+    ns = torch.full((capi.MAX_CAMS, H, W), -1, dtype=torch.int32, device="cuda")
+    fid = R.load(f)
+    try:
+        R.render(fid, cams, W, H, "f32", out=(rgba, ns))
+        torch.cuda.synchronize()
+        assert bool((ns >= 0).all()) and bool((rgba[..., 3] >= 0).all())
+        rng = np.random.default_rng(12)
+        m = 400
+        px = np.stack([rng.integers(0, capi.MAX_CAMS, m), rng.integers(0, H, m), rng.integers(0, W, m)], 1)
+        px[0] = [capi.MAX_CAMS - 1, H - 1, W - 1]
+        px[1] = [capi.MAX_CAMS - 1, H // 2, W // 2]
+        sel = torch.as_tensor((px[:, 0] * H + px[:, 1]) * W + px[:, 2], device="cuda")
+        g = rgba.view(-1, 4)[sel].cpu().numpy()
+        n = ns.view(-1)[sel].cpu().numpy()
+    finally:
+        del rgba, ns
+        torch.cuda.empty_cache()
+        R.unload(fid)
+    ref = render_fp64(f, cams, W, H, pixels=px)
+    mx, _, _ = compare_render(g, n, ref, TOL)
+    assert mx <= TOL and ref["n"].sum() > 100
