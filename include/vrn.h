@@ -117,7 +117,9 @@ typedef enum {
 typedef struct {
   vrn_dtype compute;          /* MLP arithmetic: VRN_F32 (FP32 MFMA), VRN_F16 or
                                  VRN_BF16 (MFMA, FP32 accumulate); march,
-                                 transmittance and compositing are FP32 always */
+                                 transmittance and compositing are FP32 always.
+                                 VRN_F16 needs hidden activations within the FP16
+                                 range (|x| <= 65504); beyond it they overflow */
   int32_t output;             /* vrn_output; alpha is 1 - T in every mode */
   uint32_t march_budget;      /* lattice steps per march round, 0 = default */
   float exposure_ev;          /* exposure in stops for VRN_OUT_SRGB */
