@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--shares", type=int, default=8,
                     help="also time the head path as N equal row shares of the frame, one share at a time "
                          "(the work of each of N GPUs under a static row split); 0 = off")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the unbounded-scene path (stereo 2x2048^2) and the grid-pruning pass "
+                         "on the house field (added to the JSON line as `extras`)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain 1 GiB device copy (to scale profiler byte counters)")
     return ap.parse_args()
@@ -135,6 +138,54 @@ def time_shares(R, fid, frames, W, H, compute, n, steps, warmup):
     mean = float(np.mean([s["ms"] for s in out]))
     return {"n": n, "path": compute, "steps": steps, "bands": out,
             "max_over_mean_ms": max(s["ms"] for s in out) / mean}
+
+
+def time_extras(R, house16):
+    """Beyond the headline frame: the unbounded scene (L-infinity contraction,
+    exponential sample table) as a stereo 2x2048^2 frame in FP32 and FP16,
+    and the grid-pruning pass (4 points per occupied voxel, alpha = 0.2) over
+    the house field's 512^3 grid with its FP16 tables.  HIP events on the
+    launch stream, inputs resident."""
+    import torch
+    from paper_2311_02542_amd import capi, synth
+    stream = torch.cuda.current_stream()
+
+    def events(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    cams = synth.cameras_unbounded(2, 2048, 2048)
+    for path, dtype in (("f32", np.float32), ("f16", np.float16)):
+        fid = R.load(synth.field_unbounded(table_dtype=dtype))
+        rgba = torch.zeros((2, 2048, 2048, 4), device="cuda")
+        s0 = R.stats()
+        ms = events(lambda: R.render(fid, cams, 2048, 2048, path, out=(rgba, None)), 10)
+        d = {k: v - s0[k] for k, v in R.stats().items()}
+        R.unload(fid)
+        out[f"unbounded_stereo_2048_{path}"] = {
+            "ms": ms, "rays_per_s": 2 * 2048 * 2048 / (ms * 1e-3),
+            "samples_per_ray": d["samples"] / max(d["rays"], 1),
+            "lattice_tests_per_ray": d["march_steps"] / max(d["rays"], 1),
+            "levels_per_sample": d["level_fetches"] / max(d["samples"], 1)}
+    G = int(house16["occ_res"])
+    occupied = int(np.unpackbits(np.asarray(house16["occ_bits"], np.uint32).view(np.uint8)).sum())
+    fid = R.load(house16)
+    bits = torch.zeros(((G ** 3 + 31) // 32,), dtype=torch.int32, device="cuda")
+    for path in ("f16", "f32"):
+        ms = events(lambda: capi.vrn_prune_grid(R.ctx, fid, 0.2, bits, None, 4, path), 5)
+        kept = int(np.unpackbits(bits.cpu().numpy().view(np.uint8)).sum())
+        out[f"prune_house512_{path}_mlp"] = {"ms": ms, "occupied_voxels": occupied, "kept_voxels": kept,
+                                             "points_per_s": 4 * occupied / (ms * 1e-3)}
+    R.unload(fid)
+    return out
 
 
 def pq_error(R, fid, field_ref, cams, W, H, compute, n_px, seed=0):
@@ -298,6 +349,9 @@ def main():
         print(f"bench: {args.shares} row shares of path {head}", file=sys.stderr, flush=True)
         line["row_shares"] = time_shares(R, fids[head], frames, W, H, head, args.shares,
                                          min(args.steps, 20), min(args.warmup, 5))
+    if args.extras:
+        print("bench: unbounded scene and grid pruning", file=sys.stderr, flush=True)
+        line["extras"] = time_extras(R, field16)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     R.close()
