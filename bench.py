@@ -142,10 +142,13 @@ def time_shares(R, fid, frames, W, H, compute, n, steps, warmup):
 
 def time_extras(R, house16):
     """Beyond the headline frame: the unbounded scene (L-infinity contraction,
-    exponential sample table) as a stereo 2x2048^2 frame in FP32 and FP16,
-    and the grid-pruning pass (4 points per occupied voxel, alpha = 0.2) over
-    the house field's 512^3 grid with its FP16 tables.  HIP events on the
-    launch stream, inputs resident."""
+    exponential sample table) as a stereo 2x2048^2 frame in FP32 and FP16;
+    the paper's LOD and resolution statements on the house frame; GPU and
+    one-process oracle rates of the smaller workloads (64^2 blob field,
+    1024^2 room, 2048^2 eye of the 3.2 m blob field); and the grid-pruning
+    pass (4 points per occupied voxel, alpha = 0.2) over the house field's
+    512^3 grid with its FP16 tables.  HIP events on the launch stream, inputs
+    resident."""
     import torch
     from paper_2311_02542_amd import capi, synth
     stream = torch.cuda.current_stream()
@@ -175,6 +178,56 @@ def time_extras(R, house16):
             "samples_per_ray": d["samples"] / max(d["rays"], 1),
             "lattice_tests_per_ray": d["march_steps"] / max(d["rays"], 1),
             "levels_per_sample": d["level_fetches"] / max(d["samples"], 1)}
+    # the paper's measurable statements on the house frame (FP16 path, 20 frames of the walk):
+    # LOD against all levels, a coarser LOD bias, and half the resolution
+    variants = {"lod_on": (house16, 2048), "lod_off": (dict(house16, lod_enable=0), 2048),
+                "lod_bias_-1": (dict(house16, lod_bias=-1.0), 2048),
+                "lod_bias_-2": (dict(house16, lod_bias=-2.0), 2048), "half_res_lod_on": (house16, 1024)}
+    for name, (fld, W) in variants.items():
+        fid = R.load(fld)
+        r = time_path(R, fid, synth.cameras_house_stereo(range(25), W, W), W, W, "f16", 20, 5)
+        R.unload(fid)
+        st = r["stats"]
+        out[f"house_stereo_{name}"] = {"W": W, "ms": float(np.mean(r["lat_ms"])),
+                                       "levels_per_sample": st["level_fetches"] / max(st["samples"], 1)}
+        del r
+    # the smaller benchmark workloads: GPU rays/s per path
+    blob, room = synth.field_blobs64(), synth.field_room256()
+    room16 = dict(room, tables=room["tables"].astype(np.float16))
+    b3_16, b3_32 = synth.field_blobs_3m2(), synth.field_blobs_3m2(table_dtype=np.float32)
+    cases = [("blobs64_64x64", blob, blob, synth.cameras_blobs64(1, 64, 64), 64, 200),
+             ("room256_1024x1024", room, room16, synth.cameras_room256(1), 1024, 20),
+             ("blobs_3m2_2048x2048", b3_32, b3_16, synth.cameras_walk_3m2(32)[:1], 2048, 20)]
+    from oracle.render import all_pixels, render_fp64
+    for name, f32_field, f16_field, cams, W, reps in cases:
+        res = {}
+        for path in ("f32", "f16", "bf16"):
+            if path == "bf16" and W != 2048:
+                continue
+            fid = R.load(f32_field if path == "f32" else f16_field)
+            rgba = torch.zeros((len(cams), W, W, 4), device="cuda")
+            s0 = R.stats()
+            ms = events(lambda: R.render(fid, cams, W, W, path, out=(rgba, None)), reps)
+            d = {k: v - s0[k] for k, v in R.stats().items()}
+            R.unload(fid)
+            res[path] = {"ms": ms, "rays_per_s": len(cams) * W * W / (ms * 1e-3),
+                         "samples_per_s": d["samples"] / (reps + 1) / (ms * 1e-3)}
+        # the oracle, one process: the whole 64^2 image, else a 256^2 crop (the central
+        # one, and for the 2048^2 eye also the one with the most content)
+        crops = {"full": (0, 0, W)} if W <= 256 else {"central": ((W - 256) // 2, (W - 256) // 2, 256)}
+        if W == 2048:
+            alpha = rgba[0, :, :, 3].double()
+            win = torch.nn.functional.avg_pool2d(alpha[None, None], 256, stride=32)[0, 0]
+            k = int(torch.argmax(win))
+            crops["content"] = ((k // win.shape[1]) * 32, (k % win.shape[1]) * 32, 256)
+        for cname, (r0, c0, n) in crops.items():
+            px = all_pixels(len(cams), W, W, rows=np.arange(r0, r0 + n), cols=np.arange(c0, c0 + n))
+            t0 = time.perf_counter()
+            ref = render_fp64(f32_field, cams, W, W, pixels=px)
+            dt = time.perf_counter() - t0
+            res[f"oracle_{cname}"] = {"rows_cols": [r0, c0, n], "rays_per_s": px.shape[0] / dt,
+                                      "samples_per_s": float(ref["n"].sum()) / dt, "processes": 1}
+        out[name] = res
     G = int(house16["occ_res"])
     occupied = int(np.unpackbits(np.asarray(house16["occ_bits"], np.uint32).view(np.uint8)).sum())
     fid = R.load(house16)
