@@ -346,3 +346,62 @@ def test_maximum_pixels_in_one_call(R):
     ref = render_fp64(f, cams, W, H, pixels=px)
     mx, _, _ = compare_render(g, n, ref, TOL)
     assert mx <= TOL and ref["n"].sum() > 100
+
+
+def test_two_threads_share_one_context(R):
+    """Calls on one context from two host threads (each with its own stream
+    and workspace, so their renders overlap on the device) give the same
+    images as sequential calls, and a failing call reports its error on its
+    own thread only (the last-error message is thread-local)."""
+    import threading
+    torch = R.torch
+    lib = capi.load_library()
+    f = synth.field_blobs64()
+    fid = R.load(f)
+    cams = synth.cameras_blobs64(8, 64, 64)
+    ref = []
+    for c in cams:
+        rgba, ns = R.render(fid, [c], 64, 64, "f32")
+        torch.cuda.synchronize()
+        ref.append((rgba.cpu().numpy(), ns.cpu().numpy()))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    nbytes = capi.vrn_workspace_bytes(R.ctx)
+    wss = [torch.zeros(nbytes, dtype=torch.uint8, device="cuda") for _ in streams]
+    for ws, st in zip(wss, streams):
+        capi.vrn_workspace_init(R.ctx, ws, stream=st)
+    outs = [(torch.zeros((1, 64, 64, 4), device="cuda"), torch.zeros((1, 64, 64), dtype=torch.int32, device="cuda"))
+            for _ in cams]
+    torch.cuda.synchronize()
+    # the main thread's own last error, which the worker's failure must not touch
+    with pytest.raises(capi.VrnError):
+        capi.vrn_unload_field(R.ctx, 987654)
+    main_msg = lib.vrn_last_error().decode()
+    failures, worker_err = [], {}
+
+    def worker(k):
+        try:
+            for _ in range(3):
+                for i in range(k, len(cams), 2):
+                    capi.vrn_render(R.ctx, fid, [cams[i]], 64, 64, outs[i][0], outs[i][1], "f32",
+                                    workspace=wss[k], stream=streams[k])
+            if k == 1:
+                try:
+                    capi.vrn_render(R.ctx, fid, [dict(cams[0], fx=np.float32(-1.0))], 64, 64, outs[0][0], None,
+                                    "f32", workspace=wss[k], stream=streams[k])
+                except capi.VrnError as e:
+                    worker_err["status"], worker_err["msg"] = e.status, lib.vrn_last_error().decode()
+            streams[k].synchronize()
+        except Exception as e:          # re-raised on the main thread below
+            failures.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    R.unload(fid)
+    assert not failures, failures
+    for (rgba, ns), (r_rgba, r_ns) in zip(outs, ref):
+        assert np.array_equal(rgba.cpu().numpy(), r_rgba) and np.array_equal(ns.cpu().numpy(), r_ns)
+    assert worker_err["status"] == capi.VRN_ERR_INVALID_ARG and "fx, fy > 0" in worker_err["msg"]
+    assert lib.vrn_last_error().decode() == main_msg
