@@ -147,9 +147,11 @@ void vrn_destroy(vrn_ctx* ctx);
 /* Thread-local description of the last failure on this thread. */
 const char* vrn_last_error(void);
 
-/* Validate a field and copy it into library-owned device memory (tables as
- * given, occupancy bits plus a coarse block mip, MLP weights re-laid out for
- * MFMA in FP32, FP16 and BF16).  The field stays resident until unloaded. */
+/* Validate a field -- the multiresolution hash grid of Sec. 4 (after iNGP),
+ * the density and color MLPs of Sec. 6 and the binary occupancy grid of
+ * Sec. 4.3 -- and copy it into library-owned device memory (tables as given,
+ * occupancy bits plus a coarse block mip, MLP weights re-laid out for MFMA in
+ * FP32, FP16 and BF16).  The field stays resident until unloaded. */
 vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* desc, vrn_field_id* out);
 
 /* Free a field.  VRN_ERR_BUSY while renders that use it are still running.
@@ -169,7 +171,11 @@ vrn_status vrn_workspace_bytes(vrn_ctx* ctx, uint64_t* out);
 vrn_status vrn_workspace_init(vrn_ctx* ctx, void* d_workspace, uint64_t workspace_bytes,
                               void* hip_stream);
 
-/* Render n_cams (1..VRN_MAX_CAMS) cameras of W x H pixels.
+/* Render n_cams (1..VRN_MAX_CAMS) cameras of W x H pixels: per ray the
+ * occupancy march (Sec. 4.3), the hash encoding with LOD weights (Sec. 4.2.1,
+ * Eq. 3; App. D), the density and color MLPs (Sec. 6) and front-to-back
+ * compositing with early termination into PQ color (Sec. 4.1, Eq. 1-2), all
+ * in one kernel launch (the single-kernel interleave of Sec. 5).
  *   cams        host [n_cams]; validated (finite, det(R) != 0, fx, fy > 0,
  *               row_begin < row_end <= H); copied into the workspace.
  *   d_rgba      device [n_cams][H][W][4] float: PQ (or linear) RGB, alpha = 1 - T.
@@ -183,7 +189,7 @@ vrn_status vrn_render(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, 
                       uint32_t* d_nsamples, void* d_workspace, uint64_t workspace_bytes,
                       void* hip_stream);
 
-/* As vrn_render, but the cameras are already in device memory (d_cams,
+/* As vrn_render (same passages), but the cameras are already in device memory (d_cams,
  * [n_cams] vrn_camera) and are NOT validated here (use vrn_check_cameras on
  * the host copy).  Enqueues kernels only, so it can be captured in a HIP
  * graph and replayed with new camera contents. */
@@ -223,7 +229,8 @@ vrn_status vrn_march(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, u
 vrn_status vrn_encode(vrn_ctx* ctx, vrn_field_id field, const float* d_xyz, const float* d_t,
                       const float* d_r, uint32_t n, float* d_feat, void* hip_stream);
 
-/* Density + color MLPs on MFMA in the requested dtype for n samples:
+/* Density + color MLPs (Sec. 6: one hidden layer of 64 for density, two for
+ * color; sigmoid in PQ units, Sec. 4.1) on MFMA in the requested dtype for n samples:
  * d_feat [n][2L], d_dir [n][3] unit view directions -> d_sigma [n]
  * (exp of density output 0), d_rgb [n][3] (sigmoid, PQ units). */
 vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const float* d_dir,
@@ -244,7 +251,7 @@ vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const 
 vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_t points_per_voxel,
                           vrn_dtype compute, uint32_t* d_bits_out, float* d_max_opacity, void* hip_stream);
 
-/* Replace a resident field's occupancy with device bits (same layout as
+/* Replace a resident field's occupancy grid (Sec. 4.3) with device bits (same layout as
  * vrn_field_desc.occ_bits), rebuilding its bricks and coarse grids on
  * hip_stream.  Renders of this field on other streams must be ordered by
  * the caller. */
