@@ -101,6 +101,55 @@ def test_field_validation(lib):
     assert "table_dtype" in lib.vrn_last_error().decode()
 
 
+@pytest.mark.parametrize("over,status,words", [
+    (dict(n_levels=0), capi.VRN_ERR_UNSUPPORTED, "n_levels"),
+    (dict(log2_T=3), capi.VRN_ERR_UNSUPPORTED, "log2_T"),
+    (dict(occ_res=0), capi.VRN_ERR_UNSUPPORTED, "occ_res"),
+    (dict(sh_bands=0), capi.VRN_ERR_UNSUPPORTED, "sh_bands"),
+    (dict(geo_out=8), capi.VRN_ERR_UNSUPPORTED, "geo_out"),
+    (dict(tables=None), capi.VRN_ERR_INVALID_ARG, "NULL"),
+    (dict(weights=None), capi.VRN_ERR_INVALID_ARG, "NULL"),
+    (dict(occ_bits=None), capi.VRN_ERR_INVALID_ARG, "NULL"),
+    (dict(level_res=None), capi.VRN_ERR_INVALID_ARG, "NULL"),
+    (dict(t_min=-1e-4), capi.VRN_ERR_INVALID_ARG, "t_min"),
+    (dict(extent=-1.0), capi.VRN_ERR_INVALID_ARG, "extent"),
+    (dict(dt=float("inf")), capi.VRN_ERR_INVALID_ARG, "dt"),
+    (dict(contraction=2), capi.VRN_ERR_INVALID_ARG, "contraction"),
+    (dict(contraction=1), capi.VRN_ERR_INVALID_ARG, "aabb_min = -2"),
+    (dict(step_growth=1.0), capi.VRN_ERR_INVALID_ARG, "step_growth"),
+    (dict(step_growth=-0.5), capi.VRN_ERR_INVALID_ARG, "step_growth"),
+    (dict(step_growth=0.01, max_lattice=0), capi.VRN_ERR_INVALID_ARG, "max_lattice"),
+    (dict(step_growth=0.01, max_lattice=70000), capi.VRN_ERR_INVALID_ARG, "max_lattice"),
+    (dict(lod_enable=1, base_res=0.0), capi.VRN_ERR_INVALID_ARG, "base_res"),
+    (dict(lod_enable=1, lod_bias=float("nan")), capi.VRN_ERR_INVALID_ARG, "lod_bias"),
+    (dict(lod_enable=1, lod_radius_scale=0.0), capi.VRN_ERR_INVALID_ARG, "lod_radius_scale"),
+])
+def test_field_validation_more(lib, over, status, words):
+    """Every descriptor check runs on the host before the context is touched
+    (a NULL context here), with its own status and message."""
+    assert _desc_status(lib, synth.field_blobs64(), **over) == status
+    assert words in lib.vrn_last_error().decode()
+
+
+def test_contracted_field_geometry_checks(lib):
+    f = synth.field_unbounded()
+    assert _desc_status(lib, f) == capi.VRN_ERR_INVALID_ARG                  # valid; NULL ctx
+    assert "ctx" in lib.vrn_last_error().decode()
+    assert _desc_status(lib, f, extent=8.0) == capi.VRN_ERR_INVALID_ARG
+    assert "extent = 4" in lib.vrn_last_error().decode()
+    assert _desc_status(lib, f, radius=0.0) == capi.VRN_ERR_INVALID_ARG
+    assert "radius" in lib.vrn_last_error().decode()
+
+
+def test_level_resolution_bounds(lib):
+    f = synth.field_blobs64()
+    for bad in (0, (1 << 20) + 1):
+        res = np.array(f["level_res"], np.uint32)
+        res[-1] = bad
+        assert _desc_status(lib, dict(f, level_res=res)) == capi.VRN_ERR_INVALID_ARG
+        assert "level_res" in lib.vrn_last_error().decode()
+
+
 def test_field_file_round_trip_two_readers(tmp_path):
     """The writer's files are read back identically by the oracle's reader and
     by the product binding's descriptor marshalling."""

@@ -405,3 +405,24 @@ def test_two_threads_share_one_context(R):
         assert np.array_equal(rgba.cpu().numpy(), r_rgba) and np.array_equal(ns.cpu().numpy(), r_ns)
     assert worker_err["status"] == capi.VRN_ERR_INVALID_ARG and "fx, fy > 0" in worker_err["msg"]
     assert lib.vrn_last_error().decode() == main_msg
+
+
+def test_non_finite_fields_are_rejected(R):
+    """Tables and weights must be finite (LOD-skipped levels multiply by zero
+    only safely then): a NaN in an FP32 table, an infinity in an FP16 table
+    and a NaN among the MLP weights are each refused on the host, and the
+    context stays usable."""
+    f = synth.field_blobs64()
+    bad32 = dict(f, tables=f["tables"].copy())
+    bad32["tables"][3, 100, 1] = np.nan
+    bad16 = dict(f, tables=f["tables"].astype(np.float16))
+    bad16["tables"][7, 5, 0] = np.inf
+    mlp = {k: v.copy() for k, v in f["mlp"].items()}
+    mlp["W4"][10, 20] = np.nan
+    badw = dict(f, mlp=mlp)
+    for bad, what in ((bad32, "hash tables"), (bad16, "hash tables"), (badw, "MLP weights")):
+        with pytest.raises(capi.VrnError) as ei:
+            R.load(bad)
+        assert ei.value.status == capi.VRN_ERR_INVALID_ARG and what in str(ei.value)
+    rgba, ns = gpu_render(R, f, synth.cameras_blobs64(1, 32, 32), 32, 32)
+    assert ns.sum() > 0
