@@ -426,3 +426,42 @@ def test_non_finite_fields_are_rejected(R):
         assert ei.value.status == capi.VRN_ERR_INVALID_ARG and what in str(ei.value)
     rgba, ns = gpu_render(R, f, synth.cameras_blobs64(1, 32, 32), 32, 32)
     assert ns.sum() > 0
+
+
+def test_argument_errors_enqueue_nothing(R):
+    """Each invalid argument of the render and stage entry points is refused
+    on the host with its status and message, leaves the output untouched
+    (nothing was enqueued) and leaves the context usable."""
+    torch = R.torch
+    f = synth.field_room256(log2_T=14)             # LOD on, so vrn_encode needs t and r
+    fid = R.load(f)
+    cams = synth.cameras_room256(1, 32, 32)
+    rgba = torch.full((1, 32, 32, 4), -1.0, device="cuda")
+    small_ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    cases = [
+        (lambda: capi.vrn_render(R.ctx, fid, cams, 32, 32, rgba, None, 7, workspace=R.ws), "opts.compute"),
+        (lambda: capi.vrn_render(R.ctx, fid, cams, 32, 32, rgba, None, "f32", output=5, workspace=R.ws),
+         "opts.output"),
+        (lambda: capi.vrn_render(R.ctx, fid, cams, 32, 32, rgba, None, "f32", output="srgb", exposure_ev=100.0,
+                                 workspace=R.ws), "exposure_ev"),
+        (lambda: capi.vrn_render(R.ctx, fid, cams, 32, 32, rgba, None, "f32", workspace=small_ws),
+         "workspace too small"),
+        (lambda: capi.vrn_render(R.ctx, fid, cams, 32, 32, None, None, "f32", workspace=R.ws), "d_rgba"),
+        (lambda: capi.vrn_render_device_cams(R.ctx, fid, R.ws, 17, 32, 32, rgba, None, "f32", workspace=R.ws),
+         "n_cams"),
+        (lambda: capi.vrn_encode(R.ctx, fid, rgba, None, None, 4, rgba), "LOD fields need d_t"),
+        (lambda: capi.vrn_mlp(R.ctx, fid, rgba, rgba, 4, 5, rgba, rgba), "compute"),
+        (lambda: capi.vrn_march(R.ctx, fid, cams, 32, 32, None, 4, rgba), "NULL"),
+        (lambda: capi.vrn_rays(R.ctx, cams, 32, 32, rgba, rgba, rgba, scale=0.0), "scale"),
+    ]
+    for call, words in cases:
+        with pytest.raises(capi.VrnError) as ei:
+            call()
+        assert ei.value.status == capi.VRN_ERR_INVALID_ARG and words in str(ei.value), (words, str(ei.value))
+    torch.cuda.synchronize()
+    assert bool((rgba == -1.0).all())
+    capi.vrn_encode(R.ctx, fid, rgba, rgba, rgba, 0, rgba)      # n = 0: nothing to do, no error
+    out, ns = R.render(fid, cams, 32, 32, "f32")
+    torch.cuda.synchronize()
+    R.unload(fid)
+    assert int(ns.sum()) > 0
