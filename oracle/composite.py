@@ -17,6 +17,7 @@ import numpy as np
 
 
 def new_state(n):
+    """Per-ray compositing state (Sec. 4.1, Eq. 2)."""
     st = {"T": np.ones(n), "C": np.zeros((n, 3)), "n": np.zeros(n, np.int64),
           "levels": np.zeros(n, np.int64)}
     for s in ("lo", "star", "hi"):
@@ -28,12 +29,14 @@ def new_state(n):
 
 
 def thresholds(t_min, band):
+    """Termination thresholds with the tie band around t_min (reading R15)."""
     return {"lo": t_min * (1.0 + band), "star": t_min, "hi": t_min * (1.0 - band)}
 
 
 def step(st, rows, sigma, rgb, dt, t_min, band, levels=None):
     """Composite one sample for each ray index in ``rows`` (in order); dt is
-    the step length (a scalar, or one per sample)."""
+    the step length (a scalar, or one per sample).
+    Sec. 4.1, Eq. 2; termination per reading R15."""
     alpha = 1.0 - np.exp(-np.asarray(sigma, np.float64) * np.asarray(dt, np.float32).astype(np.float64))
     T = st["T"][rows]
     st["C"][rows] += (T * alpha)[:, None] * rgb
@@ -54,7 +57,8 @@ def step(st, rows, sigma, rgb, dt, t_min, band, levels=None):
 
 
 def finish(st):
-    """Rays that ran out of samples keep their final state for every end."""
+    """Rays that ran out of samples keep their final state for every end.
+    Sec. 4.1, Eq. 2 (final transmittance and alpha)."""
     for s in ("lo", "star", "hi"):
         nd = ~st[s + "_done"]
         st[s + "_C"][nd] = st["C"][nd]
@@ -65,7 +69,8 @@ def finish(st):
 
 
 def composite_ray(sigma, rgb, dt, t_min, band=1e-4):
-    """Single-ray convenience wrapper: returns (C, A, n) at the FP64 rule."""
+    """Single-ray convenience wrapper: returns (C, A, n) at the FP64 rule.
+    Sec. 4.1, Eq. 2; reading R15."""
     st = new_state(1)
     rows = np.array([0])
     for j in range(len(sigma)):

@@ -38,11 +38,14 @@ def lod_weights(ls, n_levels):
 
 
 def is_dense(n_l, table_size):
+    """Dense storage of a level whose (N+1)^3 lattice points fit the table
+    (Sec. 4, after iNGP; reading R7)."""
     return (int(n_l) + 1) ** 3 <= int(table_size)
 
 
 def level_index(c, n_l, table_size, primes):
-    """Table index of integer lattice corners c [..., 3] at one level."""
+    """Table index of integer lattice corners c [..., 3] at one level.
+    Dense index or the iNGP spatial hash (Sec. 4; reading R9)."""
     c = np.asarray(c, np.int64)
     if is_dense(n_l, table_size):
         s = int(n_l) + 1
@@ -57,7 +60,9 @@ def level_index(c, n_l, table_size, primes):
 def encode(field, x32, weights=None):
     """Features [n, 2L] (level-major, feature fastest) for FP32 positions.
 
-    weights: [n, L] LOD weights or None (all levels weight 1)."""
+    weights: [n, L] LOD weights or None (all levels weight 1).
+    Sec. 4 (multiresolution hash grid), Sec. 4.2.1 Eq. 3 weights, App. D
+    (levels of weight 0 are not read); readings R8, R10."""
     x32 = np.asarray(x32, np.float32)
     n = x32.shape[0]
     L = int(field["n_levels"])

@@ -8,6 +8,7 @@ import numpy as np
 
 
 def load_field(prefix):
+    """Reads the field files of this repository (npz + json); no passage of the paper."""
     with open(prefix + ".json") as fh:
         meta = json.load(fh)
     if meta.get("format") != "vrn-field-1":

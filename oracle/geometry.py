@@ -30,11 +30,13 @@ F32 = np.float32
 
 
 def is_contracted(field):
+    """Whether the field uses the L-infinity contraction (Sec. 4; reading R31)."""
     return bool(field.get("contraction", 0))
 
 
 def lattice_table(field):
-    """Canonical FP32 sample distances t_k (k < max_lattice) and steps."""
+    """Canonical FP32 sample distances t_k (k < max_lattice) and steps.
+    Sec. 6 exponential sample distances; reading R30."""
     dt = F32(field["dt"])
     growth = F32(field.get("step_growth", 0.0))
     K = int(field["max_lattice"])
@@ -47,7 +49,8 @@ def lattice_table(field):
 
 def pipeline_field(field):
     """The field as the occupancy / hash stages see it: contracted fields use
-    the cube [-2, 2]^3 as their AABB."""
+    the cube [-2, 2]^3 as their AABB.
+    Sec. 4 contraction (reading R31): the grids cover the contracted cube."""
     if not is_contracted(field):
         return field
     f = dict(field)
@@ -57,7 +60,8 @@ def pipeline_field(field):
 
 
 def contract32(x, field):
-    """Canonical FP32 contraction of world points x [..., 3]."""
+    """Canonical FP32 contraction of world points x [..., 3].
+    Sec. 4 L-infinity contraction in the canonical FP32 order (reading R31)."""
     c = np.asarray(field["center"], F32)
     ir = F32(field["inv_radius"])
     u = np.stack([(x[..., a] - c[a]) * ir for a in range(3)], axis=-1).astype(F32)
@@ -70,6 +74,7 @@ def contract32(x, field):
 
 
 def contract64(x, field):
+    """Sec. 4 L-infinity contraction in FP64 (reading R31)."""
     c = np.asarray(field["center"], F32).astype(np.float64)
     u = (np.asarray(x, np.float64) - c) * np.float64(F32(field["inv_radius"]))
     m = np.max(np.abs(u), axis=-1, keepdims=True)

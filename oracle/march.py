@@ -26,11 +26,13 @@ F32 = np.float32
 
 
 def cell_scale(field):
+    """Cells per unit length of the occupancy grid (Sec. 4.3; reading R13)."""
     return F32(np.float64(field["occ_res"]) / np.float64(F32(field["extent"])))
 
 
 def slab_fp64(o, d, aabb_min, extent):
-    """Entry / exit parameters of rays o + t d with the cube [amin, amin+extent]."""
+    """Entry / exit parameters of rays o + t d with the cube [amin, amin+extent].
+    Sec. 4.3; reading R13 (FP64 slab test, padded)."""
     o64 = np.asarray(o, np.float64)
     d64 = np.asarray(d, np.float64)
     lo = np.asarray(aabb_min, F32).astype(np.float64)
@@ -53,7 +55,8 @@ def slab_fp64(o, d, aabb_min, extent):
 
 
 def lattice_range(t_near, t_far, dt):
-    """Inclusive k range [k_lo, k_hi] padded by one step; k_hi = -1 if no hit."""
+    """Inclusive k range [k_lo, k_hi] padded by one step; k_hi = -1 if no hit.
+    Sec. 4.3; readings R11 and R13."""
     dt = np.float64(F32(dt))
     hit = t_far >= np.maximum(t_near, 0.0) - dt
     with np.errstate(invalid="ignore"):
@@ -65,12 +68,13 @@ def lattice_range(t_near, t_far, dt):
 
 
 def lattice_t(k, dt):
-    """Canonical FP32 lattice parameter t_k = (k + 0.5) * dt."""
+    """Canonical FP32 lattice parameter t_k = (k + 0.5) * dt.  Reading R11 (uniform lattice)."""
     return (np.asarray(k).astype(F32) + F32(0.5)) * F32(dt)
 
 
 def canonical_positions(o, d, k, dt):
-    """FP32 sample positions o + t_k d for o, d [n, 3] and k [n, K]."""
+    """FP32 sample positions o + t_k d for o, d [n, 3] and k [n, K].
+    Reading R13 (canonical FP32 geometry)."""
     tk = lattice_t(k, dt)
     o = np.asarray(o, F32)
     d = np.asarray(d, F32)
@@ -78,7 +82,7 @@ def canonical_positions(o, d, k, dt):
 
 
 def canonical_cells(x, field):
-    """Continuous cell coordinates q, integer cells and validity for FP32 x."""
+    """Continuous cell coordinates q, integer cells and validity for FP32 x.  Sec. 4.3; reading R13."""
     amin = np.asarray(field["aabb_min"], F32)
     cs = cell_scale(field)
     q = np.stack([(x[..., a] - amin[a]) * cs for a in range(3)], axis=-1)
@@ -89,6 +93,7 @@ def canonical_cells(x, field):
 
 
 def occupied(c, valid, field):
+    """Occupancy bit of a valid cell (Sec. 4.3)."""
     g = int(field["occ_res"])
     bits = np.asarray(field["occ_bits"], np.uint32)
     cc = np.where(valid[..., None], c, 0)
@@ -98,13 +103,15 @@ def occupied(c, valid, field):
 
 
 def uses_table(field):
+    """Whether samples come from the FP32 table (Sec. 6; reading R30) rather than the uniform lattice."""
     return is_contracted(field) or float(field.get("step_growth", 0.0)) > 0.0
 
 
 def sample_points(field, o, d, k):
     """Canonical FP32 sample points for o, d [n, 3] and lattice indices k
     [n, K]: returns (y, t) with y in the coordinates the occupancy and hash
-    grids use (world for bounded fields, contracted for unbounded ones)."""
+    grids use (world for bounded fields, contracted for unbounded ones).
+    Readings R11, R13, R30, R31."""
     if not uses_table(field):
         return canonical_positions(o, d, k, field["dt"])
     tab, _ = lattice_table(field)
@@ -116,7 +123,7 @@ def sample_points(field, o, d, k):
 
 
 def sample_range(field, o, d):
-    """Inclusive lattice index range [k_lo, k_hi] worth testing per ray."""
+    """Inclusive lattice index range [k_lo, k_hi] worth testing per ray.  Sec. 4.3; readings R11-R14."""
     if is_contracted(field):
         n = o.shape[0]
         return np.zeros(n, np.int64), np.full(n, int(field["max_lattice"]) - 1, np.int64)
@@ -133,7 +140,9 @@ def sample_range(field, o, d):
 def dense_masked_march(field, o, d, chunk=512):
     """Evaluated lattice indices per ray, in increasing k, capped.
 
-    Returns (ks [n, M] int64 padded with -1, counts [n])."""
+    Returns (ks [n, M] int64 padded with -1, counts [n]).
+    Sec. 4.3 (occupancy grid), as its plain definition: every lattice sample
+    tested; reading R14 for the cap."""
     o = np.asarray(o, F32)
     d = np.asarray(d, F32)
     n = o.shape[0]

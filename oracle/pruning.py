@@ -30,6 +30,7 @@ F32 = np.float32
 
 
 def voxel_offsets(points_per_voxel):
+    """App. C, four evenly placed points per voxel (reading R29)."""
     if points_per_voxel == 4:
         q, t = 0.25, 0.75
         return np.array([[q, q, q], [t, t, q], [t, q, t], [q, t, t]], F32)
@@ -42,7 +43,8 @@ def voxel_offsets(points_per_voxel):
 
 
 def voxel_points(field, cells, offsets):
-    """Canonical FP32 points [n_vox, n_pts, 3] for integer cells [n_vox, 3]."""
+    """Canonical FP32 points [n_vox, n_pts, 3] for integer cells [n_vox, 3].
+    Sec. 4.3 and App. C; reading R29."""
     G = int(field["occ_res"])
     cell = F32(np.float64(F32(field["extent"])) / np.float64(G))
     amin = np.asarray(field["aabb_min"], F32)
@@ -54,7 +56,8 @@ def grid_prune_fp64(field, alpha, points_per_voxel=4, band=1e-5, batch=65536, vo
     """Returns (bits_out uint32 words, max_opacity [G^3] float64 (NaN where the
     voxel was not occupied or not evaluated), tie [G^3] bool: |opacity - alpha|
     <= band*alpha).  ``voxels`` restricts the evaluation to a subset of linear
-    voxel indices (bits outside it are then meaningless)."""
+    voxel indices (bits outside it are then meaningless).
+    Sec. 4.3 grid pruning with App. C's points; reading R29."""
     G = int(field["occ_res"])
     bits = np.asarray(field["occ_bits"], np.uint32)
     n = G ** 3

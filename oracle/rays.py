@@ -22,7 +22,8 @@ F32 = np.float32
 
 
 def canonical_rays(cam, i, j):
-    """FP32 origins and unit directions for integer pixel arrays i (col), j (row)."""
+    """FP32 origins and unit directions for integer pixel arrays i (col), j (row).
+    Reading R20 (camera model) and R13 (canonical FP32 order)."""
     c2w = np.asarray(cam["c2w"], F32)
     fx, fy, cx, cy = (F32(cam[k]) for k in ("fx", "fy", "cx", "cy"))
     fi = np.asarray(i).astype(F32) + F32(0.5)
@@ -37,7 +38,7 @@ def canonical_rays(cam, i, j):
 
 
 def fp64_directions(cam, i, j):
-    """Exact-arithmetic (FP64) unit ray directions."""
+    """Exact-arithmetic (FP64) unit ray directions.  Reading R20 (camera model), in FP64."""
     c2w = np.asarray(cam["c2w"], F32).astype(np.float64)
     fx, fy, cx, cy = (np.float64(F32(cam[k])) for k in ("fx", "fy", "cx", "cy"))
     a = (np.asarray(i, np.float64) + 0.5 - cx) / fx
@@ -48,7 +49,8 @@ def fp64_directions(cam, i, j):
 
 def cone_pitch(cam, i, j, scale=1.0):
     """Base radius at unit distance: distance between the unit directions of
-    pixel (i, j) and its right neighbour (i + 1, j), FP64."""
+    pixel (i, j) and its right neighbour (i + 1, j), FP64.
+    Sec. 4.2.1 base radius; reading R5."""
     d0 = fp64_directions(cam, i, j)
     d1 = fp64_directions(cam, np.asarray(i) + 1, j)
     return scale * np.linalg.norm(d1 - d0, axis=-1)

@@ -22,6 +22,7 @@ from .sh import sh_basis
 
 
 def all_pixels(n_cams, W, H, rows=None, cols=None):
+    """Pixel list (camera, row, col) in framebuffer order; no passage."""
     rows = np.arange(H) if rows is None else np.asarray(rows)
     cols = np.arange(W) if cols is None else np.asarray(cols)
     c, r, x = np.meshgrid(np.arange(n_cams), rows, cols, indexing="ij")
@@ -45,6 +46,7 @@ def contracted_level_star(field, cam, cols, rows, o, t):
 
 
 def _render_batch(field, cam, rows, cols, band, rank_block, keep_k):
+    """Sec. 4-5 per-pixel pipeline for one batch of pixels of one camera."""
     o, d = canonical_rays(cam, cols, rows)
     n = o.shape[0]
     lod = bool(field["lod_enable"])
@@ -111,7 +113,8 @@ def render_fp64(field, cams, W, H, pixels=None, band=1e-4, batch=4096, rank_bloc
     FP64 termination rule, n (composited samples), the tie-range ends
     rgba_lo/n_lo and rgba_hi/n_hi, tie (bool), levels (hash levels read
     summed over the composited samples) and, with keep_k, the evaluated
-    lattice indices per pixel (uncapped by termination)."""
+    lattice indices per pixel (uncapped by termination).
+    Sec. 4-5: march (4.3), LOD hash encoding (4.2.1), MLPs (6), compositing (4.1)."""
     if pixels is None:
         pixels = all_pixels(len(cams), W, H)
     pixels = np.asarray(pixels, np.int64)

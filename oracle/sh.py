@@ -19,7 +19,8 @@ import numpy as np
 
 
 def _legendre_poly_part(l_max, z):
-    """Q[l][m] = P_l^m(z) / sin^m(theta), no Condon-Shortley phase."""
+    """Q[l][m] = P_l^m(z) / sin^m(theta), no Condon-Shortley phase.
+    Associated Legendre part of the real SH basis (reading R18)."""
     Q = {}
     for m in range(l_max + 1):
         dfact = 1.0
@@ -34,7 +35,7 @@ def _legendre_poly_part(l_max, z):
 
 
 def sh_basis(dirs, bands):
-    """[n, bands^2] real SH of unit directions (FP64)."""
+    """[n, bands^2] real SH of unit directions (FP64).  Real SH of the view direction (reading R18)."""
     d = np.asarray(dirs, np.float64)
     x, y, z = d[..., 0], d[..., 1], d[..., 2]
     l_max = bands - 1
