@@ -183,7 +183,8 @@ def dense_masked_march(field, o, d, chunk=512):
 
 def dda_traverse(o, d, aabb_min, extent, g):
     """Independent FP64 Amanatides-Woo traversal of one ray through the G^3
-    grid: list of (t_in, t_out, (cx, cy, cz)) in order of t."""
+    grid: list of (t_in, t_out, (cx, cy, cz)) in order of t.  A pin for the
+    march of Sec. 4.3, from the published traversal, not from this module."""
     o = np.asarray(o, np.float64)
     d = np.asarray(d, np.float64)
     s = g / np.float64(F32(extent))

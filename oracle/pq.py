@@ -41,7 +41,8 @@ def pq_to_linear(e):
 
 
 def srgb_oetf(v):
-    """sRGB transfer function (IEC 61966-2-1) on linear values in [0, 1]."""
+    """sRGB transfer function (IEC 61966-2-1) on linear values in [0, 1]
+    (display output, reading R33)."""
     v = np.clip(np.asarray(v, np.float64), 0.0, 1.0)
     return np.where(v <= 0.0031308, 12.92 * v, 1.055 * np.power(v, 1.0 / 2.4) - 0.055)
 
