@@ -64,7 +64,8 @@ typedef struct {
   uint32_t hash_primes[3];    /* spatial hash (c0*p0 ^ c1*p1 ^ c2*p2) mod T */
   float base_res;             /* s: LOD level-0 resolution (Sec. 4.2.1) */
   float growth;               /* f: per-level scale factor, > 1 when lod_enable */
-  vrn_dtype table_dtype;      /* VRN_F32 or VRN_F16 */
+  int32_t table_dtype;        /* a vrn_dtype: VRN_F32 or VRN_F16 (int32_t, so that any value a
+                                 caller stores is well defined to read; others are refused) */
   const void* tables;         /* host [L][T][F], feature fastest, finite values */
   uint32_t mlp_in;            /* density MLP input width, must be 2 * L */
   uint32_t mlp_hidden;        /* must be 64 */
@@ -115,7 +116,7 @@ typedef enum {
 } vrn_output;
 
 typedef struct {
-  vrn_dtype compute;          /* MLP arithmetic: VRN_F32 (FP32 MFMA), VRN_F16 or
+  int32_t compute;            /* a vrn_dtype, the MLP arithmetic: VRN_F32 (FP32 MFMA), VRN_F16 or
                                  VRN_BF16 (MFMA, FP32 accumulate); march,
                                  transmittance and compositing are FP32 always.
                                  VRN_F16 needs hidden activations within the FP16
