@@ -258,6 +258,16 @@ vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_
  * the caller. */
 vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* hip_stream);
 
+/* ---- debugging ---- */
+
+/* Counters of a library built with -DVRN_DEBUG_CHECKS (synchronises the
+ * device first): out[0] hash-table offsets outside their level, out[1]
+ * brick and out[2] coarse-grid indices outside the grid, out[3] framebuffer
+ * writes outside the frame, out[4] NaN encoded features, out[5] NaN MLP
+ * outputs.  The kernels count instead of trapping.  reset != 0 zeroes the
+ * counters after reading.  VRN_ERR_UNSUPPORTED in release builds. */
+vrn_status vrn_debug_counters(vrn_ctx* ctx, uint64_t out[6], int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vrn_mlp": (c_i32, [c_vp, c_u32, c_vp, c_vp, c_u32, c_i32, c_vp, c_vp, c_vp]),
         "vrn_prune_grid": (c_i32, [c_vp, c_u32, c_f, c_u32, c_i32, c_vp, c_vp, c_vp]),
         "vrn_set_occupancy": (c_i32, [c_vp, c_u32, c_vp, c_vp]),
+        "vrn_debug_counters": (c_i32, [c_vp, P(c_u64), ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -335,6 +336,18 @@ def vrn_prune_grid(ctx, fid, alpha, bits_out, max_opacity=None, points_per_voxel
     c = DTYPES[compute] if isinstance(compute, str) else int(compute)
     _check(lib.vrn_prune_grid(ctx, fid, float(alpha), int(points_per_voxel), c, _ptr(bits_out),
                               _ptr(max_opacity), _stream(stream)), lib)
+
+
+DEBUG_SLOTS = ("table_offset", "brick_index", "coarse_index", "pixel_write", "nan_feature", "nan_mlp_output")
+
+
+def vrn_debug_counters(ctx, reset=False) -> dict:
+    """Counters of a library built with -DVRN_DEBUG_CHECKS (raises
+    VRN_ERR_UNSUPPORTED on a release build)."""
+    lib = load_library()
+    out = (c_u64 * len(DEBUG_SLOTS))()
+    _check(lib.vrn_debug_counters(ctx, out, int(bool(reset))), lib)
+    return dict(zip(DEBUG_SLOTS, (int(v) for v in out)))
 
 
 def vrn_set_occupancy(ctx, fid, bits, stream=None):

@@ -694,6 +694,19 @@ vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_
   return VRN_OK;
 }
 
+vrn_status vrn_debug_counters(vrn_ctx* ctx, uint64_t out[6], int reset) {
+  if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hipSetDevice(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  unsigned long long v[kDbgSlots] = {};
+  if (e == hipSuccess) e = debug_counters(v, reset != 0);
+  if (e == hipErrorNotSupported) return fail(VRN_ERR_UNSUPPORTED, "library built without VRN_DEBUG_CHECKS");
+  if (e != hipSuccess) return hip_fail(e, "debug counters");
+  for (int i = 0; i < kDbgSlots; ++i) out[i] = v[i];
+  return VRN_OK;
+}
+
 vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* stream) {
   if (!ctx || !d_bits) return fail(VRN_ERR_INVALID_ARG, "ctx or d_bits is NULL");
   std::lock_guard<std::mutex> lock(ctx->mu);

@@ -426,6 +426,7 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
     if ((unsigned)cx < (unsigned)G && (unsigned)cy < (unsigned)G && (unsigned)cz < (unsigned)G) {
       const int bx = cx >> F.cshift, by = cy >> F.cshift, bz = cz >> F.cshift;
       const uint32_t ci = (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz);
+      VRN_DEBUG_COUNT(ci >= F.Gc * F.Gc * F.Gc, kDbgCoarse);
       if (!bit_set(coarse, ci)) {
         if (!bit_set(coarse + kCoarseWords, ci)) {
           // a clear block starts a run of empty blocks: jump to its end
@@ -478,6 +479,7 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
         const int kx = cx >> 2, ky = cy >> 2, kz = cz >> 2;
         const int brick = kx + (int)F.Gb * (ky + (int)F.Gb * kz);
         if (brick != r.brick) {
+          VRN_DEBUG_COUNT((uint32_t)brick >= F.Gb * F.Gb * F.Gb, kDbgBrick);
           const unsigned long long b = F.bricks[brick];
           r.brick = brick;
           r.blo = (uint32_t)b;
@@ -625,6 +627,11 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     }
     uint32_t off[8];
     corner_offsets(F, P, (F.dense_mask >> (4 * j)) & 0xFu, i0, off);
+#ifdef VRN_DEBUG_CHECKS
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      VRN_DEBUG_COUNT(off[c] - P.base >= (F.Tmask + 1u) * (F.table_f16 ? 4u : 8u), kDbgTableOffset);
+#endif
     float v0[8], v1[8];
     if (TAB16) {
       uint32_t raw[8];
@@ -655,6 +662,7 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     }
     feat[2 * j] = w * acc0;
     feat[2 * j + 1] = w * acc1;
+    VRN_DEBUG_COUNT(feat[2 * j] != feat[2 * j] || feat[2 * j + 1] != feat[2 * j + 1], kDbgFeature);
     ++fetches;
   }
 }
@@ -693,6 +701,11 @@ __device__ __forceinline__ void encode_point_h2(const FieldDev& F, const LevelDe
     for (int a = 0; a < 3; ++a) i0[a] = base_corner_fast(uh[a], P.s_hi, P.below_n, fr[a]);
     uint32_t off[8];
     corner_offsets(F, P, (F.dense_mask >> (4 * j)) & 0xFu, i0, off);
+#ifdef VRN_DEBUG_CHECKS
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      VRN_DEBUG_COUNT(off[c] - P.base >= (F.Tmask + 1u) * (F.table_f16 ? 4u : 8u), kDbgTableOffset);
+#endif
     half2_t v[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c)
@@ -702,6 +715,12 @@ __device__ __forceinline__ void encode_point_h2(const FieldDev& F, const LevelDe
     const half2_t e01 = h2_lerp(v[4], v[5], fx), e11 = h2_lerp(v[6], v[7], fx);
     const half2_t e0 = h2_lerp(e00, e10, fy), e1 = h2_lerp(e01, e11, fy);
     hfeat[j] = __builtin_bit_cast(uint32_t, h2_lerp(e0, e1, fz) * h2_splat(w));
+#ifdef VRN_DEBUG_CHECKS
+    {
+      const half2_t hv = __builtin_bit_cast(half2_t, hfeat[j]);
+      VRN_DEBUG_COUNT(hv[0] != hv[0] || hv[1] != hv[1], kDbgFeature);
+    }
+#endif
     ++fetches;
   }
 }

@@ -94,6 +94,27 @@ struct RenderArgs {
 };
 
 // launchers (kernels.hip)
+// Debug builds (-DVRN_DEBUG_CHECKS) count, instead of trapping on, hash-table
+// offsets outside their level, brick and coarse-grid indices outside the
+// grid, framebuffer writes outside the frame and NaN features or MLP
+// outputs; vrn_debug_counters reads the counts.  Release builds compile none
+// of it.
+enum DebugSlot { kDbgTableOffset = 0, kDbgBrick, kDbgCoarse, kDbgPixel, kDbgFeature, kDbgMlpNaN, kDbgSlots };
+#ifdef VRN_DEBUG_CHECKS
+extern __device__ unsigned long long vrn_debug_counts[kDbgSlots];
+#define VRN_DEBUG_COUNT(cond, slot)                                 \
+  do {                                                              \
+    if (cond) atomicAdd(&vrn_debug_counts[(slot)], 1ull);           \
+  } while (0)
+#else
+#define VRN_DEBUG_COUNT(cond, slot) \
+  do {                              \
+  } while (0)
+#endif
+// Copy (and optionally zero) the debug counters; hipErrorNotSupported in
+// release builds.
+hipError_t debug_counters(unsigned long long out[kDbgSlots], bool reset);
+
 hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t s);
 int render_blocks_per_cu(const FieldDev& F, int compute);
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);

@@ -22,6 +22,10 @@
 
 namespace vrn {
 
+#ifdef VRN_DEBUG_CHECKS
+__device__ unsigned long long vrn_debug_counts[kDbgSlots];
+#endif
+
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // exp for compositing: the FP32 path keeps the library expf; the 16-bit
@@ -184,6 +188,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
         v.z = srgb_oetf(v.z * A.exposure);
       }
     }
+    VRN_DEBUG_COUNT((uint64_t)pix >= (uint64_t)A.n_cams * A.H * A.W, kDbgPixel);
     reinterpret_cast<float4*>(A.rgba)[pix] = v;
     if (A.nsamples) A.nsamples[pix] = n;
     ++st_rays;
@@ -336,6 +341,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
 
     // ---- 4. composite (FP32), terminate --------------------------------
     if (has) {
+      VRN_DEBUG_COUNT(so0 != so0 || sl0 != sl0 || sl1 != sl1 || sl2 != sl2, kDbgMlpNaN);
       constexpr bool kFast = MODE != 0;
       const float sd = comp_exp<kFast>(so0) * sdt;
       const float trans = comp_exp<kFast>(-sd);
@@ -703,6 +709,21 @@ hipError_t launch_set_occupancy(const FieldDev& F, const uint32_t* bits, hipStre
   hipLaunchKernelGGL(dilate_coarse_kernel, dim3((words + 255) / 256), dim3(256), 0, s, F,
                      const_cast<uint32_t*>(F.coarse_dil));
   return hipGetLastError();
+}
+
+hipError_t debug_counters(unsigned long long out[kDbgSlots], bool reset) {
+#ifdef VRN_DEBUG_CHECKS
+  hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(vrn_debug_counts), sizeof(unsigned long long) * kDbgSlots);
+  if (e == hipSuccess && reset) {
+    const unsigned long long zero[kDbgSlots] = {};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(vrn_debug_counts), zero, sizeof(zero));
+  }
+  return e;
+#else
+  (void)out;
+  (void)reset;
+  return hipErrorNotSupported;
+#endif
 }
 
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s) {
