@@ -216,12 +216,85 @@ __device__ __forceinline__ bool bit_set(const uint32_t* bits, uint32_t idx) {
   return (bits[idx >> 5] >> (idx & 31u)) & 1u;
 }
 
+// Contracted fields, outside the unit L-inf ball: the canonical samples lie
+// on the image of the straight ray under C.  Over a stretch [t_a, t_b] on
+// which one axis i dominates u at both ends, with the same sign and
+// |u_i| > 1, it dominates throughout (|u_j| - |u_i| is convex in t and
+// |u_i| linear), so y_i = sign (2 - 1/|u_i|) is monotone, and y_j = a b with
+// a = 2 - 1/|u_i| in (1, 2) and b = u_j / |u_i| both monotone: the products
+// of their end values bound y_j.  CurveStart holds the start of a stretch
+// (sample r.k); curve_bound returns the box, in cell units, that holds the
+// curve from there to sample kb, or false when the dominance condition
+// fails.  Canonical sample positions lie within FP32 error (far below a
+// hundredth of a cell) of the curve.
+struct CurveStart {
+  float b[3], s, a;  // b = u / m at the start (the dominant axis' entry is unused)
+  int axis;
+};
+
+__device__ __forceinline__ void curve_u(const FieldDev& F, const Ray& r, float t, float u[3]) {
+  u[0] = (r.ox + t * r.dx - F.center[0]) * F.inv_radius;
+  u[1] = (r.oy + t * r.dy - F.center[1]) * F.inv_radius;
+  u[2] = (r.oz + t * r.dz - F.center[2]) * F.inv_radius;
+}
+
+__device__ __forceinline__ void curve_dominant(const float u[3], int& axis, float& m) {
+  const float ax = fabsf(u[0]), ay = fabsf(u[1]), az = fabsf(u[2]);
+  axis = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  m = fmaxf(ax, fmaxf(ay, az));
+}
+
+// False when sample r.k lies in the unit ball (no curve bound applies).
+__device__ __forceinline__ bool curve_start(const FieldDev& F, const Ray& r, CurveStart& c) {
+  float u[3], m;
+  curve_u(F, r, F.lat[r.k], u);
+  curve_dominant(u, c.axis, m);
+  c.s = c.axis == 0 ? u[0] : (c.axis == 1 ? u[1] : u[2]);
+  c.a = 2.0f - 1.0f / m;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.b[a] = a == c.axis ? 0.0f : u[a] / m;
+  return m > 1.0f;
+}
+
+__device__ __forceinline__ bool curve_bound(const FieldDev& F, const Ray& r, const CurveStart& c, int kb,
+                                            float qlo[3], float qhi[3]) {
+  const float g4 = 0.25f * (float)F.G;
+  float ub[3];
+  curve_u(F, r, F.lat[kb], ub);
+  int ib;
+  float mb;
+  curve_dominant(ub, ib, mb);
+  const float sb = ib == 0 ? ub[0] : (ib == 1 ? ub[1] : ub[2]);
+  if (ib != c.axis || (c.s > 0.0f) != (sb > 0.0f) || !(mb > 1.0f)) return false;
+  const float ab = 2.0f - 1.0f / mb;
+  const float alo = fminf(c.a, ab), ahi = fmaxf(c.a, ab);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float lo, hi;
+    if (a == c.axis) {
+      lo = c.s > 0.0f ? alo : -ahi;
+      hi = c.s > 0.0f ? ahi : -alo;
+    } else {
+      const float ba = c.b[a], bb = ub[a] / mb;
+      const float blo = fminf(ba, bb), bhi = fmaxf(ba, bb);
+      lo = fminf(fminf(alo * blo, alo * bhi), fminf(ahi * blo, ahi * bhi));
+      hi = fmaxf(fmaxf(alo * blo, alo * bhi), fmaxf(ahi * blo, ahi * bhi));
+    }
+    qlo[a] = (lo + 2.0f) * g4;
+    qhi[a] = (hi + 2.0f) * g4;
+  }
+  return true;
+}
+
 // Jump past the lattice samples that stay inside the empty box of `size`
 // cells with corner o (cell units), shrunk by delta.  The jump is taken only
 // when the current sample (q) and the landing sample both lie in the shrunk
 // box: by convexity every lattice sample in between lies in it too, and
 // delta >= twice the FP32 error of q, so no sample whose canonical cell is
-// occupied is ever passed.  Returns true if r.k moved.
+// occupied is ever passed.  Beyond the unit ball of a contracted field the
+// samples follow a curve: there a doubling search takes the farthest
+// r.k + 2^j (j >= 1) whose curve box, padded by a hundredth of a cell, lies
+// in the shrunk box.  Returns true if r.k moved.
 template <int GEO>
 __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float q[3], int ox, int oy, int oz,
                                          float size) {
@@ -234,8 +307,25 @@ __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float 
     // map straight segments to straight segments
     const float a = 0.25f * (float)F.G, b = 0.75f * (float)F.G;
     if (!(ox * size >= a && oy * size >= a && oz * size >= a && (ox + 1) * size <= b && (oy + 1) * size <= b &&
-          (oz + 1) * size <= b))
-      return false;
+          (oz + 1) * size <= b)) {
+      CurveStart c;
+      if (!curve_start(F, r, c)) return false;
+      int best = r.k;
+      for (int step = 2; step < (1 << 20); step *= 2) {
+        const int kb = min(r.k + step, r.k_hi);
+        if (kb <= best) break;
+        float ql[3], qh[3];
+        if (!curve_bound(F, r, c, kb, ql, qh)) break;
+        if (!(ql[0] - 0.01f >= lo[0] && qh[0] + 0.01f <= hi[0] && ql[1] - 0.01f >= lo[1] && qh[1] + 0.01f <= hi[1] &&
+              ql[2] - 0.01f >= lo[2] && qh[2] + 0.01f <= hi[2]))
+          break;
+        best = kb;
+        if (kb == r.k_hi) break;
+      }
+      if (best < r.k + 2) return false;
+      r.k = best + 1;
+      return true;
+    }
   }
   // approximate exit parameter (reciprocals need not be exact: the landing
   // sample is re-tested with the canonical arithmetic below)
@@ -314,73 +404,32 @@ __device__ __forceinline__ float coarse_run(const FieldDev& F, const uint32_t* d
   return t_exit;
 }
 
-// Contracted fields, outside the unit L-inf ball: the canonical samples lie
-// on the image of the straight ray under C.  Over a stretch [t_a, t_b] on
-// which one axis i dominates u at both ends, with the same sign and
-// |u_i| > 1, it dominates throughout (|u_j| - |u_i| is convex in t and
-// |u_i| linear), so y_i = sign (2 - 1/|u_i|) is monotone, and y_j = a b with
-// a = 2 - 1/|u_i| in (1, 2) and b = u_j / |u_i| both monotone: the products
-// of their end values bound y_j.  When every coarse block touched by that
-// box (padded by a hundredth of a cell) is clear, every sample of the
-// stretch, whose canonical position is within FP32 error of the curve, has
-// an empty cell.  A doubling search returns the farthest lattice index
+// When every coarse block touched by the curve's box from r.k to a sample
+// (padded by a hundredth of a cell) is clear, every sample of that stretch
+// has an empty cell.  A doubling search returns the farthest lattice index
 // r.k + 2^j whose stretch from r.k passes (r.k itself when none does).
 __device__ __forceinline__ int contracted_run(const FieldDev& F, const uint32_t* dil, const Ray& r) {
-  const float g4 = 0.25f * (float)F.G;
   const float inv_cb = 1.0f / (float)(1u << F.cshift);
   const int Gc = (int)F.Gc;
-  auto ucoord = [&](float t, float u[3]) {
-    u[0] = (r.ox + t * r.dx - F.center[0]) * F.inv_radius;
-    u[1] = (r.oy + t * r.dy - F.center[1]) * F.inv_radius;
-    u[2] = (r.oz + t * r.dz - F.center[2]) * F.inv_radius;
-  };
-  auto dominant = [](const float u[3], int& axis, float& m) {
-    const float ax = fabsf(u[0]), ay = fabsf(u[1]), az = fabsf(u[2]);
-    axis = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
-    m = fmaxf(ax, fmaxf(ay, az));
-  };
-  float ua[3];
-  ucoord(F.lat[r.k], ua);
-  int ia;
-  float ma;
-  dominant(ua, ia, ma);
-  const float sa = ia == 0 ? ua[0] : (ia == 1 ? ua[1] : ua[2]);
-  if (!(ma > 1.0f)) return r.k;
-  const float aa = 2.0f - 1.0f / ma;
+  CurveStart c;
+  if (!curve_start(F, r, c)) return r.k;
   // does the stretch [r.k, kb] stay in clear blocks?
   auto stretch_clear = [&](int kb) -> bool {
-    float ub[3];
-    ucoord(F.lat[kb], ub);
-    int ib;
-    float mb;
-    dominant(ub, ib, mb);
-    const float sb = ib == 0 ? ub[0] : (ib == 1 ? ub[1] : ub[2]);
-    if (ib != ia || (sa > 0.0f) != (sb > 0.0f) || !(mb > 1.0f)) return false;
-    const float ab = 2.0f - 1.0f / mb;
-    const float alo = fminf(aa, ab), ahi = fmaxf(aa, ab);
+    float ql[3], qh[3];
+    if (!curve_bound(F, r, c, kb, ql, qh)) return false;
     int b0[3], b1[3];
     bool fits = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      float lo, hi;
-      if (a == ia) {
-        lo = sa > 0.0f ? alo : -ahi;
-        hi = sa > 0.0f ? ahi : -alo;
-      } else {
-        const float ba = ua[a] / ma, bb = ub[a] / mb;
-        const float blo = fminf(ba, bb), bhi = fmaxf(ba, bb);
-        lo = fminf(fminf(alo * blo, alo * bhi), fminf(ahi * blo, ahi * bhi));
-        hi = fmaxf(fmaxf(alo * blo, alo * bhi), fmaxf(ahi * blo, ahi * bhi));
-      }
-      b0[a] = (int)floorf(((lo + 2.0f) * g4 - 0.01f) * inv_cb);
-      b1[a] = (int)floorf(((hi + 2.0f) * g4 + 0.01f) * inv_cb);
+      b0[a] = (int)floorf((ql[a] - 0.01f) * inv_cb);
+      b1[a] = (int)floorf((qh[a] + 0.01f) * inv_cb);
       fits = fits && b0[a] >= 0 && b1[a] < Gc && b1[a] - b0[a] <= 1;
     }
     if (!fits) return false;
     bool clear = true;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int x = b0[0] + (c & 1), y = b0[1] + ((c >> 1) & 1), z = b0[2] + (c >> 2);
+    for (int k = 0; k < 8; ++k) {
+      const int x = b0[0] + (k & 1), y = b0[1] + ((k >> 1) & 1), z = b0[2] + (k >> 2);
       if (x <= b1[0] && y <= b1[1] && z <= b1[2])
         clear = clear && !bit_set(dil, (uint32_t)x + (uint32_t)Gc * ((uint32_t)y + (uint32_t)Gc * (uint32_t)z));
     }
@@ -813,7 +862,7 @@ __device__ __forceinline__ v4f zero4() {
   return z;
 }
 
-// Biases are added after the MFMA accumulation: the density bias is large
+// The density output bias is added after the MFMA accumulation: it is large
 // (several units) next to the products, and adding it last rounds it once.
 __device__ __forceinline__ v4f add_bias4(v4f v, const float* sb, int base, int g) {
   v4f r;
@@ -822,8 +871,8 @@ __device__ __forceinline__ v4f add_bias4(v4f v, const float* sb, int base, int g
   return r;
 }
 
-// The 16-bit paths start the FP32 accumulator at the bias (one 16-byte LDS
-// read, no adds); the FP32 path adds it after accumulation for accuracy.
+// Hidden layers start the FP32 accumulator at the bias (one 16-byte LDS read,
+// no adds); so do all layers of the 16-bit paths.
 __device__ __forceinline__ v4f bias_acc(const float* sb, int base, int g) {
   const float4 b = *reinterpret_cast<const float4*>(sb + base + 4 * g);
   v4f r;
@@ -849,7 +898,7 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
   const int g = lane >> 4;
   v4f h[4];
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) h[ot] = zero4();
+  for (int ot = 0; ot < 4; ++ot) h[ot] = bias_acc(sb, kB1 + 16 * ot, g);
 #pragma unroll
   for (int s4 = 0; s4 < 2; ++s4) {
     if ((uint32_t)s4 < d1_groups) {
@@ -864,7 +913,7 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     }
   }
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) h[ot] = relu4(add_bias4(h[ot], sb, kB1 + 16 * ot, g));
+  for (int ot = 0; ot < 4; ++ot) h[ot] = relu4(h[ot]);
   v4f o = zero4();
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
@@ -878,7 +927,7 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
   v4f c1[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) {
-    c1[ot] = zero4();
+    c1[ot] = bias_acc(sb, kB3 + 16 * ot, g);
     const float4 w0 = sw[kW32_C1 / 4 + (ot * 2 + 0) * 64 + lane];
     c1[ot] = mfma_f32(w0.x, o[0], c1[ot]);
     c1[ot] = mfma_f32(w0.y, o[1], c1[ot]);
@@ -891,11 +940,11 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     c1[ot] = mfma_f32(w1.w, shs[3], c1[ot]);
   }
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) c1[ot] = relu4(add_bias4(c1[ot], sb, kB3 + 16 * ot, g));
+  for (int ot = 0; ot < 4; ++ot) c1[ot] = relu4(c1[ot]);
   v4f c2[4];
 #pragma unroll
   for (int ot = 0; ot < 4; ++ot) {
-    c2[ot] = zero4();
+    c2[ot] = bias_acc(sb, kB4 + 16 * ot, g);
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const float4 w = sw[kW32_C2 / 4 + (ot * 4 + it) * 64 + lane];
@@ -906,7 +955,7 @@ __device__ __forceinline__ void mlp_tile_f32(const float4* __restrict__ sw, cons
     }
   }
 #pragma unroll
-  for (int ot = 0; ot < 4; ++ot) c2[ot] = relu4(add_bias4(c2[ot], sb, kB4 + 16 * ot, g));
+  for (int ot = 0; ot < 4; ++ot) c2[ot] = relu4(c2[ot]);
   // color output layer (64 -> 3) on the VALU: 13 of the 16 MFMA output rows
   // would be padding.  Lane (s, g) holds hidden units 16 it + 4 g + r of
   // sample s; the weights W5[16 it + 4 g + r][c] sit in the C3 fragments of

@@ -29,11 +29,16 @@ def _blobs64_exponential():
     return f
 
 
-@pytest.mark.parametrize("case", ["unbounded", "blobs64_exponential"])
+@pytest.mark.parametrize("case", ["unbounded", "unbounded_4x64x48", "blobs64_exponential"])
 def test_march_bit_exact(R, case):
     torch = R.torch
     if case == "unbounded":
         f, cams, W, H = synth.field_unbounded(), synth.cameras_unbounded(2, 40, 32), 40, 32
+    elif case == "unbounded_4x64x48":
+        # four poses: rays that leave the room cross empty bricks and blocks
+        # of the far field, where the march skips along bounds of the
+        # contracted curve
+        f, cams, W, H = synth.field_unbounded(), synth.cameras_unbounded(4, 64, 48), 64, 48
     else:
         f, cams, W, H = _blobs64_exponential(), synth.cameras_blobs64(4, 48, 40), 48, 40
     fid = R.load(f)
