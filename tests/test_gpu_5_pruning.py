@@ -66,6 +66,39 @@ def test_prune_room256_sampled(R):
     assert 0 < g.sum() < sample.size
 
 
+@pytest.mark.parametrize("compute", ["f32", "f16"])
+def test_prune_house512_sampled(R, compute):
+    """The timed pruning workload's field (house, 512^3, FP16 tables, 4
+    points per voxel) at full size, checked on 3,000 sampled occupied voxels.
+    alpha = 0.87 sits at the median of their opacities, so about half are
+    pruned.  FP32 MLP: opacities within 1e-5 relative and decisions exact
+    outside the tie band.  FP16 MLP: opacity within 1e-3 absolute (two
+    FP16 units in the last place at these opacities, ~0.87), and decisions
+    equal wherever the FP64 opacity is farther than that from alpha."""
+    f = synth.field_house512()
+    G, alpha = 512, 0.87
+    fid = R.load(f)
+    bits, mx = _gpu_prune(R, fid, G, alpha, 4, compute)
+    R.unload(fid)
+    occ = np.isfinite(mx)
+    assert occ.sum() == 4027518
+    rng = np.random.default_rng(0)
+    sample = rng.choice(np.nonzero(occ)[0], 3000, replace=False)
+    _, ref_mx, tie = grid_prune_fp64(f, alpha, 4, voxels=sample)
+    g = synth.unpack_bits(bits, G).ravel()[sample]
+    o = ref_mx[sample] >= alpha
+    err = np.abs(mx[sample] - ref_mx[sample])
+    print(f"house512 {compute}: max opacity error {err.max():.3g}, kept {g.sum()} of {sample.size}")
+    if compute == "f32":
+        np.testing.assert_allclose(mx[sample], ref_mx[sample], rtol=1e-5)
+        assert not ((g != o) & ~tie[sample]).any()
+    else:
+        assert err.max() <= 1e-3
+        far = np.abs(ref_mx[sample] - alpha) > 1e-3
+        assert not ((g != o) & far).any()
+    assert 0.2 * sample.size < g.sum() < 0.8 * sample.size
+
+
 def test_pruned_field_renders_like_oracle(R):
     torch = R.torch
     f = synth.field_blobs64()
