@@ -353,6 +353,21 @@ def field_unbounded(table_dtype=np.float32) -> dict:
     return f
 
 
+def field_unbounded_sparse_far(table_dtype=np.float32) -> dict:
+    """The unbounded scene's field with other occupancy: the inner cube empty
+    and isolated occupied cells (0.2 %) beyond it, so that most occupied
+    8-cell blocks of the far field consist of empty 4-cell bricks that rays
+    cross before their first hit (inputs for march tests)."""
+    f = field_unbounded(table_dtype)
+    g = int(f["occ_res"])
+    occ = rng_for(6, 5).random((g, g, g)) < 0.002
+    c = np.arange(g)
+    inner = (c >= g // 4) & (c < 3 * g // 4)
+    occ[np.ix_(inner, inner, inner)] = False
+    f["occ_bits"] = pack_bits(occ)
+    return f
+
+
 def cameras_unbounded(n=2, W=256, H=256):
     rng = rng_for(6, 4)
     out = []

@@ -29,7 +29,7 @@ def _blobs64_exponential():
     return f
 
 
-@pytest.mark.parametrize("case", ["unbounded", "unbounded_4x64x48", "blobs64_exponential"])
+@pytest.mark.parametrize("case", ["unbounded", "unbounded_4x64x48", "unbounded_sparse_far", "blobs64_exponential"])
 def test_march_bit_exact(R, case):
     torch = R.torch
     if case == "unbounded":
@@ -39,6 +39,10 @@ def test_march_bit_exact(R, case):
         # of the far field, where the march skips along bounds of the
         # contracted curve
         f, cams, W, H = synth.field_unbounded(), synth.cameras_unbounded(4, 64, 48), 64, 48
+    elif case == "unbounded_sparse_far":
+        # isolated far-field cells: rays cross many empty bricks of occupied
+        # blocks beyond the unit ball, the other branch of those skips
+        f, cams, W, H = synth.field_unbounded_sparse_far(), synth.cameras_unbounded(2, 40, 32), 40, 32
     else:
         f, cams, W, H = _blobs64_exponential(), synth.cameras_blobs64(4, 48, 40), 48, 40
     fid = R.load(f)
