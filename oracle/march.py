@@ -11,8 +11,9 @@ exponential spacing and gives no render-time sampler):
   each op rounded:  t_k = (k + 0.5) * dt,  x = o + t_k * d,
   q = (x - aabb_min) * cell_scale with cell_scale = fp32(G / extent),
   cell = floor(q); the sample is valid iff 0 <= cell < G on every axis;
-* the k range comes from an FP64 slab test padded by one step on each side,
-  so membership is decided by the canonical test alone;
+* the k range comes from an FP64 slab test of the cube grown by a bound on
+  the FP32 position error, padded by one step on each side, so membership is
+  decided by the canonical test alone;
 * "max samples per ray" caps EVALUATED samples (valid and occupied).
 
 ``dda_traverse`` is an independent FP64 Amanatides-Woo voxel traversal used
@@ -30,38 +31,58 @@ def cell_scale(field):
     return F32(np.float64(field["occ_res"]) / np.float64(F32(field["extent"])))
 
 
-def slab_fp64(o, d, aabb_min, extent):
-    """Entry / exit parameters of rays o + t d with the cube [amin, amin+extent].
-    Sec. 4.3; reading R13 (FP64 slab test, padded)."""
+# Bound on how far a canonical FP32 sample position (and its cell
+# coordinate) can stray from the exact point o + t d: every op of reading
+# R13 rounds once (relative 2^-24), so the error stays below
+# 2^-22 (|o| + t + |aabb_min| + 2 extent) in world units; the range below uses
+# four times that (ERR_REL = 2^-20).
+ERR_REL = 2.0 ** -20
+
+
+def reach_interval(o, d, aabb_min, extent):
+    """[t_lo, t_hi] (FP64) outside of which no canonical FP32 sample of the
+    rays o + t d can pass the cell test of the cube [amin, amin + extent]:
+    the slab test of a box that grows with t by the FP32 position error
+    bound, c0 + c1 t per side.  t_hi < t_lo when no sample can.
+    Sec. 4.3; reading R13 (membership is decided by the canonical test alone,
+    so the range only has to contain every sample that test could keep)."""
     o64 = np.asarray(o, np.float64)
     d64 = np.asarray(d, np.float64)
     lo = np.asarray(aabb_min, F32).astype(np.float64)
-    hi = lo + np.float64(F32(extent))
-    t_near = np.full(o64.shape[:-1], -np.inf)
-    t_far = np.full(o64.shape[:-1], np.inf)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        for a in range(3):
-            da = d64[..., a]
-            t1 = (lo[a] - o64[..., a]) / da
-            t2 = (hi[a] - o64[..., a]) / da
-            tmin, tmax = np.minimum(t1, t2), np.maximum(t1, t2)
-            par = da == 0
-            inside = (o64[..., a] >= lo[a]) & (o64[..., a] <= hi[a])
-            tmin = np.where(par, np.where(inside, -np.inf, np.inf), tmin)
-            tmax = np.where(par, np.where(inside, np.inf, -np.inf), tmax)
-            t_near = np.maximum(t_near, tmin)
-            t_far = np.minimum(t_far, tmax)
-    return t_near, t_far
+    ext = np.float64(F32(extent))
+    hi = lo + ext
+    c0 = ERR_REL * (np.max(np.abs(o64), axis=-1) + np.max(np.abs(lo)) + 2.0 * ext)
+    c1 = ERR_REL
+    t_lo = np.zeros(o64.shape[:-1])
+    t_hi = np.full(o64.shape[:-1], np.inf)
+
+    def constrain(alpha, beta, ge):
+        # t * alpha >= beta (ge) or t * alpha <= beta
+        nonlocal t_lo, t_hi
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = beta / alpha
+        up = (alpha < 0) if ge else (alpha > 0)        # an upper bound on t
+        dn = (alpha > 0) if ge else (alpha < 0)        # a lower bound on t
+        t_hi = np.where(up, np.minimum(t_hi, r), t_hi)
+        t_lo = np.where(dn, np.maximum(t_lo, r), t_lo)
+        never = (alpha == 0) & ((beta > 0) if ge else (beta < 0))
+        t_hi = np.where(never, -np.inf, t_hi)
+
+    for a in range(3):
+        constrain(d64[..., a] + c1, lo[a] - c0 - o64[..., a], True)
+        constrain(d64[..., a] - c1, hi[a] + c0 - o64[..., a], False)
+    return t_lo, t_hi
 
 
-def lattice_range(t_near, t_far, dt):
-    """Inclusive k range [k_lo, k_hi] padded by one step; k_hi = -1 if no hit.
-    Sec. 4.3; readings R11 and R13."""
+def lattice_range(t_lo, t_hi, dt):
+    """Inclusive k range [k_lo, k_hi] of lattice samples t_k = (k + 1/2) dt
+    that can fall in [t_lo, t_hi], padded by one step (t_k carries its own
+    rounding); k_hi = -1 if none.  Sec. 4.3; readings R11 and R13."""
     dt = np.float64(F32(dt))
-    hit = t_far >= np.maximum(t_near, 0.0) - dt
+    hit = t_hi >= t_lo
     with np.errstate(invalid="ignore"):
-        lo = np.where(np.isfinite(t_near), np.floor(t_near / dt - 0.5) - 1, 0.0)
-        hi = np.where(np.isfinite(t_far), np.ceil(t_far / dt - 0.5) + 1, -1.0)
+        lo = np.floor(np.where(hit, t_lo, 0.0) / dt - 0.5) - 1
+        hi = np.ceil(np.where(hit, t_hi, 0.0) / dt - 0.5) + 1
     k_lo = np.maximum(lo, 0.0)
     k_hi = np.where(hit, hi, -1.0)
     return k_lo.astype(np.int64), k_hi.astype(np.int64)
@@ -127,14 +148,15 @@ def sample_range(field, o, d):
     if is_contracted(field):
         n = o.shape[0]
         return np.zeros(n, np.int64), np.full(n, int(field["max_lattice"]) - 1, np.int64)
-    t_near, t_far = slab_fp64(o, d, field["aabb_min"], field["extent"])
+    t_lo, t_hi = reach_interval(o, d, field["aabb_min"], field["extent"])
     if not uses_table(field):
-        return lattice_range(t_near, t_far, field["dt"])
+        return lattice_range(t_lo, t_hi, field["dt"])
+    # table samples: every index whose FP32 entry lies in [t_lo, t_hi], one more on each side
     tab, _ = lattice_table(field)
-    hit = t_far >= np.maximum(t_near, 0.0)
-    lo = np.maximum(np.searchsorted(tab, np.where(np.isfinite(t_near), t_near, 0.0)) - 2, 0)
-    hi = np.minimum(np.searchsorted(tab, np.where(np.isfinite(t_far), t_far, 0.0)) + 1, tab.size - 1)
-    return lo.astype(np.int64), np.where(hit, hi, -1).astype(np.int64)
+    hit = t_hi >= t_lo
+    lo = np.maximum(np.searchsorted(tab, np.where(hit, t_lo, 0.0), side="left") - 1, 0)
+    hi = np.minimum(np.searchsorted(tab, np.where(hit, t_hi, 0.0), side="right"), tab.size - 1)
+    return lo.astype(np.int64), np.where(hit & (lo <= hi), hi, -1).astype(np.int64)
 
 
 def dense_masked_march(field, o, d, chunk=512):
