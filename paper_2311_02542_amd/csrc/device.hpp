@@ -86,10 +86,16 @@ __device__ __forceinline__ int table_count_le(const FieldDev& F, float t) {
   return lo;
 }
 
-// Lattice range [k_lo, k_hi] from an FP32 slab test padded by two steps on
-// each side; the canonical per-sample test alone decides membership.  With a
-// sample table the padded slab is mapped through the table; contracted
-// fields keep every table sample (all of space lies in the cube).
+// Lattice range [k_lo, k_hi] worth testing.  A canonical FP32 sample
+// position strays from the exact point o + t d by less than
+// 2^-22 (|o| + t + |aabb_min| + 2 extent) (every op rounds once), so no sample
+// outside the slab interval of the cube grown by c0 + c1 t per side, with
+// c = 2^-18 (16 times that bound, which also covers the rounding of this
+// FP32 evaluation, reciprocals included), can pass the cell test.  The range is that interval,
+// padded by two samples on each side; the canonical per-sample test alone
+// decides membership.  With a sample table the interval is mapped through
+// the table; contracted fields keep every table sample (all of space lies in
+// the cube).
 template <int GEO>
 __device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
   const float o[3] = {r.ox, r.oy, r.oz};
@@ -103,24 +109,32 @@ __device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
     r.delta = ldexpf(F.cs * M + (float)F.G + 1.0f, -20);
     return;
   }
-  float tn = 0.0f, tf = 3.0e38f;
-  bool miss = false;
+  const float amax = fmaxf(fabsf(F.amin[0]), fmaxf(fabsf(F.amin[1]), fabsf(F.amin[2])));
+  const float omax = fmaxf(fabsf(o[0]), fmaxf(fabsf(o[1]), fabsf(o[2])));
+  const float c1 = 0x1p-18f;
+  const float c0 = c1 * (omax + amax + 2.0f * F.extent);
+  float tlo = 0.0f, thi = 3.0e38f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float lo = F.amin[a], hi = F.amin[a] + F.extent;
-    if (d[a] != 0.0f) {
-      const float id = __builtin_amdgcn_rcpf(d[a]);
-      const float t1 = (lo - o[a]) * id, t2 = (hi - o[a]) * id;
-      tn = fmaxf(tn, fminf(t1, t2));
-      tf = fminf(tf, fmaxf(t1, t2));
-    } else if (o[a] < lo || o[a] > hi) {
-      miss = true;
-    }
+    // lower face: t (d + c1) >= amin - c0 - o
+    // (hardware reciprocals: their ~1 ulp is far inside the margin)
+    const float al = d[a] + c1, bl = (F.amin[a] - c0) - o[a];
+    const float rl = bl * __builtin_amdgcn_rcpf(al);
+    if (al > 0.0f) tlo = fmaxf(tlo, rl);
+    else if (al < 0.0f) thi = fminf(thi, rl);
+    else if (bl > 0.0f) thi = -1.0f;
+    // upper face: t (d - c1) <= amin + extent + c0 - o
+    const float ah = d[a] - c1, bh = ((F.amin[a] + F.extent) + c0) - o[a];
+    const float rh = bh * __builtin_amdgcn_rcpf(ah);
+    if (ah > 0.0f) thi = fminf(thi, rh);
+    else if (ah < 0.0f) tlo = fmaxf(tlo, rh);
+    else if (bh < 0.0f) thi = -1.0f;
   }
+  const bool miss = !(thi >= tlo);
   if constexpr (GEO == 0) {
-    const float klo = floorf(tn * F.inv_dt - 0.5f) - 2.0f;
-    const float khi = ceilf(fminf(tf * F.inv_dt, kmax) - 0.5f) + 2.0f;
-    if (miss || !(tf >= tn - 2.0f * F.dt) || klo > kmax) {
+    const float klo = floorf(tlo * F.inv_dt - 0.5f) - 2.0f;
+    const float khi = ceilf(fminf(thi * F.inv_dt, kmax) - 0.5f) + 2.0f;
+    if (miss || klo > kmax) {
       r.k = 0;
       r.k_hi = -1;
     } else {
@@ -128,18 +142,16 @@ __device__ __forceinline__ void lattice_range(const FieldDev& F, Ray& r) {
       r.k_hi = (int)fminf(khi, kmax);
     }
   } else {
-    if (miss || !(tf >= tn - 2.0f * F.dt)) {
+    if (miss) {
       r.k = 0;
       r.k_hi = -1;
     } else {
-      const float pad = 2.0f * F.dt + 1e-5f * tf;
-      r.k = max(table_count_le(F, tn - pad) - 1, 0);
-      r.k_hi = min(table_count_le(F, fminf(tf + pad, 3.0e38f)), (int)F.lat_K - 1);
+      r.k = max(table_count_le(F, tlo) - 2, 0);
+      r.k_hi = min(table_count_le(F, thi) + 1, (int)F.lat_K - 1);
     }
   }
   const float tcap = GEO == 0 ? kmax * F.dt : F.lat[F.lat_K - 1];
-  const float M = fmaxf(fabsf(o[0]), fmaxf(fabsf(o[1]), fabsf(o[2]))) + fminf(tf, tcap) +
-                  fmaxf(fabsf(F.amin[0]), fmaxf(fabsf(F.amin[1]), fabsf(F.amin[2])));
+  const float M = omax + fminf(fmaxf(thi, 0.0f), tcap) + amax;
   r.delta = ldexpf(F.cs * M + (float)F.G + 1.0f, -20);
 }
 
