@@ -199,6 +199,26 @@ vrn_status vrn_render_device_cams(vrn_ctx* ctx, vrn_field_id field, const vrn_ca
                                   const vrn_render_opts* opts, float* d_rgba, uint32_t* d_nsamples,
                                   void* d_workspace, uint64_t workspace_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * vrn_render_device_cams, but the render's queue, completion and statistics
+ * counters live in a static scratch array of the library (1 KiB per device,
+ * held until the process ends) instead of a workspace.  The call allocates
+ * nothing: no hipMalloc, no hipFree, no event creation (the field's tracking
+ * event is made when the field is loaded).  It enqueues a fill kernel that
+ * clears the counters, then the render kernel, on hip_stream.
+ *   d_cams      device [n_cams] vrn_camera, NOT validated (vrn_check_cameras).
+ *   d_rgba, d_nsamples as in vrn_render.
+ * Limits: n_cams 1..VRN_MAX_CAMS, W and H 1..16384, n_cams*W*H <= 2^31;
+ * anything beyond is VRN_ERR_INVALID_ARG before any device work.  Every call
+ * on one GPU shares that GPU's scratch: calls that overlap on the device (on
+ * different streams without ordering) race and give wrong images, so keep
+ * them on one stream or order them.  The stats the scratch accumulates are
+ * those of the last call and are not readable through vrn_read_stats. */
+vrn_status vrn_render_noalloc(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* d_cams,
+                              uint32_t n_cams, uint32_t W, uint32_t H, const vrn_render_opts* opts,
+                              float* d_rgba, uint32_t* d_nsamples, void* hip_stream);
+
 /* Host-side camera validation used by vrn_render (no device work). */
 vrn_status vrn_check_cameras(const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H);
 

@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                c_vp, c_vp, c_vp, c_u64, c_vp]),
         "vrn_render_device_cams": (c_i32, [c_vp, c_u32, c_vp, c_u32, c_u32, c_u32,
                                            P(VrnRenderOpts), c_vp, c_vp, c_vp, c_u64, c_vp]),
+        "vrn_render_noalloc": (c_i32, [c_vp, c_u32, c_vp, c_u32, c_u32, c_u32, P(VrnRenderOpts), c_vp,
+                                       c_vp, c_vp]),
         "vrn_check_cameras": (c_i32, [P(VrnCamera), c_u32, c_u32, c_u32]),
         "vrn_read_stats": (c_i32, [c_vp, c_vp, P(VrnStats), c_vp]),
         "vrn_rays": (c_i32, [c_vp, P(VrnCamera), c_u32, c_u32, c_u32, c_f, c_vp, c_vp, c_vp, c_vp]),
@@ -289,6 +291,17 @@ def vrn_render_device_cams(ctx, fid, d_cams, n_cams, W, H, rgba, nsamples=None, 
     _check(lib.vrn_render_device_cams(ctx, fid, _ptr(d_cams), n_cams, W, H, ctypes.byref(opts),
                                       _ptr(rgba), _ptr(nsamples), _ptr(workspace), ws_bytes,
                                       _stream(stream)), lib)
+
+
+def vrn_render_noalloc(ctx, fid, d_cams, n_cams, W, H, rgba, nsamples=None, compute="f32",
+                       linear_hdr=False, stream=None, march_budget=0):
+    """As vrn_render_device_cams, with the render's counters in the library's
+    static per-device scratch: the library allocates nothing.  Calls on one
+    GPU must not overlap on the device."""
+    lib = load_library()
+    opts = render_opts(compute, linear_hdr, march_budget)
+    _check(lib.vrn_render_noalloc(ctx, fid, _ptr(d_cams), n_cams, W, H, ctypes.byref(opts), _ptr(rgba),
+                                  _ptr(nsamples), _stream(stream)), lib)
 
 
 def vrn_check_cameras(cams, W, H) -> int:

@@ -33,6 +33,10 @@ struct Field {
   std::vector<void*> allocs;
   uint64_t bytes = 0;
   std::vector<hipEvent_t> events;  // renders in flight
+  // renders of the allocation-free entry point in flight: one event, made
+  // at load time and re-recorded by every such render (those renders share
+  // one scratch array, so the caller serialises them on the device)
+  hipEvent_t noalloc_ev = nullptr;
 };
 
 }  // namespace
@@ -46,6 +50,7 @@ struct vrn_ctx {
   std::map<uint32_t, Field*> fields;
   uint32_t next_id = 1;
   void* ws = nullptr;  // the context's own workspace
+  void* scratch = nullptr;  // this device's scratch array (vrn_render_noalloc)
 };
 
 namespace {
@@ -225,6 +230,7 @@ hipError_t upload(Field* f, const T* host, size_t count, T** out) {
 
 void free_field(Field* f) {
   for (hipEvent_t ev : f->events) hipEventDestroy(ev);
+  if (f->noalloc_ev) hipEventDestroy(f->noalloc_ev);
   for (void* p : f->allocs) hipFree(p);
   delete f;
 }
@@ -257,7 +263,7 @@ vrn_status check_opts(const vrn_render_opts* opts) {
 
 vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t n_cams, uint32_t W,
                      uint32_t H, const vrn_render_opts* opts, float* d_rgba, uint32_t* d_nsamples, void* ws,
-                     hipStream_t s) {
+                     hipStream_t s, bool noalloc = false) {
   RenderArgs a{};
   a.F = f->dev;
   a.cams = d_cams;
@@ -278,7 +284,13 @@ vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t 
   const int grid = (int)std::max<uint64_t>(1, std::min(want, cap));
   hipError_t e = launch_render(a, compute, grid, s);
   if (e != hipSuccess) return hip_fail(e, "render launch");
-  track(f, s);
+  if (!noalloc) {
+    track(f, s);
+  } else {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+      hipEventRecord(f->noalloc_ev, s);
+  }
   return VRN_OK;
 }
 
@@ -310,6 +322,13 @@ vrn_status vrn_create(int device, uint64_t hbm_budget_bytes, vrn_ctx** out) {
     hipFree(ctx->ws);
     delete ctx;
     return hip_fail(e, "workspace init");
+  }
+  // the scratch array of vrn_render_noalloc: its address on this device
+  // (taken once per device, with the device current)
+  if ((e = scratch_address(device, &ctx->scratch)) != hipSuccess) {
+    hipFree(ctx->ws);
+    delete ctx;
+    return hip_fail(e, "scratch address");
   }
   *out = ctx;
   return VRN_OK;
@@ -444,7 +463,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
       (e = upload(f, coarse_dil.data(), coarse_dil.size(), &dcd)) || (e = upload(f, w32.data(), w32.size(), &dw32)) ||
       (e = upload(f, w16.data(), w16.size(), &dw16)) || (e = upload(f, wbf.data(), wbf.size(), &dwbf)) ||
       (e = upload(f, bias.data(), bias.size(), &dbias)) ||
-      (use_table && (e = upload(f, lat.data(), lat.size(), &dlat)))) {
+      (use_table && (e = upload(f, lat.data(), lat.size(), &dlat))) ||
+      (e = hipEventCreateWithFlags(&f->noalloc_ev, hipEventDisableTiming))) {
     free_field(f);
     return e == hipErrorOutOfMemory ? fail(VRN_ERR_OUT_OF_MEMORY, "device allocation failed")
                                     : hip_fail(e, "field upload");
@@ -507,6 +527,7 @@ vrn_status vrn_unload_field(vrn_ctx* ctx, vrn_field_id field) {
   hipSetDevice(ctx->device);
   for (hipEvent_t ev : f->events)
     if (hipEventQuery(ev) == hipErrorNotReady) return fail(VRN_ERR_BUSY, "field has renders in flight");
+  if (hipEventQuery(f->noalloc_ev) == hipErrorNotReady) return fail(VRN_ERR_BUSY, "field has renders in flight");
   ctx->used -= f->bytes;
   ctx->fields.erase(field);
   free_field(f);
@@ -585,6 +606,31 @@ vrn_status vrn_render_device_cams(vrn_ctx* ctx, vrn_field_id field, const vrn_ca
                                   void* hip_stream) {
   return render_common(ctx, field, d_cams, true, n_cams, W, H, opts, d_rgba, d_nsamples, d_workspace,
                        workspace_bytes, hip_stream);
+}
+
+vrn_status vrn_render_noalloc(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* d_cams, uint32_t n_cams,
+                              uint32_t W, uint32_t H, const vrn_render_opts* opts, float* d_rgba,
+                              uint32_t* d_nsamples, void* hip_stream) {
+  if (!ctx) return fail(VRN_ERR_INVALID_ARG, "ctx is NULL");
+  if (!d_cams) return fail(VRN_ERR_INVALID_ARG, "cameras are NULL");
+  if (!d_rgba) return fail(VRN_ERR_INVALID_ARG, "d_rgba is NULL");
+  // the scratch holds the counters of one render of any size; requests
+  // beyond the render limits are refused before anything is enqueued
+  if (n_cams < 1 || n_cams > (uint32_t)kMaxCams)
+    return fail(VRN_ERR_INVALID_ARG, "n_cams must be 1..16 (the scratch serves one render of at most 16 cameras)");
+  if (W < 1 || H < 1 || W > 16384 || H > 16384 || (uint64_t)n_cams * W * H > (1ull << 31))
+    return fail(VRN_ERR_INVALID_ARG, "W and H must be 1..16384 with at most 2^31 pixels in one call");
+  vrn_status st = check_opts(opts);
+  if (st != VRN_OK) return st;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // counters start at zero: a fill kernel, not a memset (safe under capture)
+  if ((e = launch_zero(ctx->scratch, kScratchBytes, s)) != hipSuccess) return hip_fail(e, "scratch clear");
+  return do_render(ctx, f, d_cams, n_cams, W, H, opts, d_rgba, d_nsamples, ctx->scratch, s, true);
 }
 
 vrn_status vrn_read_stats(vrn_ctx* ctx, const void* ws, vrn_stats* out, void* stream) {

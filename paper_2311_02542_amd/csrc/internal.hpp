@@ -80,6 +80,10 @@ constexpr int kWsDone = 512;       // u32 blocks-finished counter
 constexpr int kWsStats = 576;      // 6 x u64: rays, samples, level fetches, march steps, rounds, tiles
 constexpr int kWsCams = 640;       // kMaxCams x vrn_camera
 constexpr int kWsBytes = 4096;
+// The allocation-free entry point keeps a render's counters (queues, done,
+// stats: everything below kWsCams) in a file-scope device array of this size.
+constexpr int kScratchBytes = 1024;
+static_assert(kScratchBytes >= kWsCams, "scratch holds every counter of a workspace");
 
 struct RenderArgs {
   FieldDev F;
@@ -118,6 +122,10 @@ hipError_t debug_counters(unsigned long long out[kDbgSlots], bool reset);
 hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t s);
 int render_blocks_per_cu(const FieldDev& F, int compute);
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);
+// Device address of the allocation-free entry point's scratch array on
+// `device`, which must be current: taken (and the array cleared) on the first
+// call per device, then returned from a per-device cache.
+hipError_t scratch_address(int device, void** out);
 hipError_t launch_rays(const vrn_camera* d_cams, uint32_t n_cams, uint32_t W, uint32_t H,
                        float scale, float* o, float* d, float* r, hipStream_t s);
 hipError_t launch_march(const FieldDev& F, const vrn_camera* d_cams, uint32_t n_cams, uint32_t W,

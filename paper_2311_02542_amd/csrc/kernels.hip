@@ -16,6 +16,8 @@
 //      or when the march leaves the grid, writing RGBA and sample counts.
 // Counters in the workspace return to zero when the last block finishes, so
 // the launch needs no memset and can be replayed from a HIP graph.
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "device.hpp"
@@ -724,6 +726,41 @@ hipError_t debug_counters(unsigned long long out[kDbgSlots], bool reset) {
   (void)reset;
   return hipErrorNotSupported;
 #endif
+}
+
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free render entry point (vrn_render_noalloc):
+// the queue, blocks-done and statistics counters of one render, laid out as
+// a workspace.  Every device the library runs on holds its own copy until
+// the process ends.  Host code must never pass `scratch` itself to a kernel
+// (in host code it is a stand-in, not a device address): it passes the
+// address scratch_address() returns for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device ordinal -> that device's copy of `scratch`
+}  // namespace
+
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  // first call on this device (the caller made it current): take the
+  // array's device address and clear the array once
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  if ((e = launch_zero(p, kScratchBytes, nullptr)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return e;
+  g_scratch_ptr.emplace(device, p);
+  *out = p;
+  return hipSuccess;
 }
 
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s) {
