@@ -166,6 +166,14 @@ vrn_status vrn_field_bytes(vrn_ctx* ctx, vrn_field_id field, uint64_t* out);
 /* Bytes of device workspace one render needs (counters, cameras, stats). */
 vrn_status vrn_workspace_bytes(vrn_ctx* ctx, uint64_t* out);
 
+/* Device bytes one render of n_cams cameras of W x H pixels of `field`
+ * needs beyond the resident field, for admission against an HBM budget: a
+ * workspace plus the caller's RGBA framebuffer ([n_cams][H][W][4] float) and
+ * sample counts ([n_cams][H][W] uint32).  No device work.  VRN_ERR_INVALID_ARG
+ * for sizes no render accepts, VRN_ERR_NOT_FOUND for an unknown field. */
+vrn_status vrn_render_bytes(vrn_ctx* ctx, vrn_field_id field, uint32_t n_cams, uint32_t W, uint32_t H,
+                            const vrn_render_opts* opts, uint64_t* out);
+
 /* Zero a caller-owned workspace with a kernel on hip_stream (safe inside
  * graph capture).  Required once before a workspace's first render; a render
  * leaves its counters at zero again, and the stats keep accumulating. */

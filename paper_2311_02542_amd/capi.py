@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vrn_field_bytes": (c_i32, [c_vp, c_u32, P(c_u64)]),
         "vrn_workspace_bytes": (c_i32, [c_vp, P(c_u64)]),
         "vrn_workspace_init": (c_i32, [c_vp, c_vp, c_u64, c_vp]),
+        "vrn_render_bytes": (c_i32, [c_vp, c_u32, c_u32, c_u32, c_u32, P(VrnRenderOpts), P(c_u64)]),
         "vrn_render": (c_i32, [c_vp, c_u32, P(VrnCamera), c_u32, c_u32, c_u32, P(VrnRenderOpts),
                                c_vp, c_vp, c_vp, c_u64, c_vp]),
         "vrn_render_device_cams": (c_i32, [c_vp, c_u32, c_vp, c_u32, c_u32, c_u32,
@@ -248,6 +249,16 @@ def vrn_workspace_bytes(ctx) -> int:
     lib = load_library()
     out = c_u64()
     _check(lib.vrn_workspace_bytes(ctx, ctypes.byref(out)), lib)
+    return int(out.value)
+
+
+def vrn_render_bytes(ctx, fid, n_cams, W, H, compute="f32") -> int:
+    """Device bytes a render of this shape needs beyond the resident field
+    (workspace, RGBA framebuffer and sample counts): the admission size."""
+    lib = load_library()
+    out = c_u64()
+    opts = render_opts(compute)
+    _check(lib.vrn_render_bytes(ctx, fid, n_cams, W, H, ctypes.byref(opts), ctypes.byref(out)), lib)
     return int(out.value)
 
 

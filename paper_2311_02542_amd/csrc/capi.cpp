@@ -39,6 +39,7 @@ struct Field {
   hipEvent_t noalloc_ev = nullptr;
 };
 
+
 }  // namespace
 
 struct vrn_ctx {
@@ -226,6 +227,18 @@ hipError_t upload(Field* f, const T* host, size_t count, T** out) {
   e = hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice);
   *out = static_cast<T*>(p);
   return e;
+}
+
+// device memory the kernels fill themselves (no host copy)
+template <typename T>
+hipError_t alloc_only(Field* f, size_t count, T** out) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16));
+  if (e != hipSuccess) return e;
+  f->allocs.push_back(p);
+  f->bytes += count * sizeof(T);
+  *out = static_cast<T*>(p);
+  return hipSuccess;
 }
 
 void free_field(Field* f) {
@@ -443,7 +456,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   }
   const uint64_t tab_bytes = n_tab * (d->table_dtype == VRN_F16 ? 2 : 4);
   const uint64_t need = tab_bytes + bricks.size() * 8 + coarse.size() * 8 + (w32.size() + bias.size()) * 4 +
-                        (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev) + lat.size() * 4;
+                        (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev) + lat.size() * 4 +
+                        bricks.size() * 4 + 256;
   if (ctx->budget && ctx->used + need > ctx->budget)
     return fail(VRN_ERR_BUDGET, "loading the field would exceed the HBM budget");
 
@@ -456,6 +470,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   unsigned long long* dbr = nullptr;
   uint32_t *dco = nullptr, *dcd = nullptr;
   float *dw32 = nullptr, *dbias = nullptr, *dlat = nullptr;
+  uint32_t *dlist = nullptr, *dcount = nullptr;
+  const std::vector<uint32_t> zeros(64, 0u);
   uint16_t *dw16 = nullptr, *dwbf = nullptr;
   if ((e = upload(f, static_cast<const uint8_t*>(d->tables), tab_bytes, &tab)) ||
       (e = upload(f, lv.data(), lv.size(), &dlv)) || (e = upload(f, bricks.data(), bricks.size(), &dbr)) ||
@@ -464,6 +480,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
       (e = upload(f, w16.data(), w16.size(), &dw16)) || (e = upload(f, wbf.data(), wbf.size(), &dwbf)) ||
       (e = upload(f, bias.data(), bias.size(), &dbias)) ||
       (use_table && (e = upload(f, lat.data(), lat.size(), &dlat))) ||
+      (e = alloc_only(f, bricks.size(), &dlist)) || (e = upload(f, zeros.data(), zeros.size(), &dcount)) ||
       (e = hipEventCreateWithFlags(&f->noalloc_ev, hipEventDisableTiming))) {
     free_field(f);
     return e == hipErrorOutOfMemory ? fail(VRN_ERR_OUT_OF_MEMORY, "device allocation failed")
@@ -474,6 +491,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.bricks = dbr;
   F.coarse = dco;
   F.coarse_dil = dcd;
+  F.brick_list = dlist;
+  F.brick_count = dcount;
   F.w32 = dw32;
   F.w16 = dw16;
   F.wbf = dwbf;
@@ -546,6 +565,21 @@ vrn_status vrn_field_bytes(vrn_ctx* ctx, vrn_field_id field, uint64_t* out) {
 vrn_status vrn_workspace_bytes(vrn_ctx* ctx, uint64_t* out) {
   if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
   *out = kWsBytes;
+  return VRN_OK;
+}
+
+vrn_status vrn_render_bytes(vrn_ctx* ctx, vrn_field_id field, uint32_t n_cams, uint32_t W, uint32_t H,
+                            const vrn_render_opts* opts, uint64_t* out) {
+  if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
+  if (n_cams < 1 || n_cams > (uint32_t)kMaxCams || W < 1 || H < 1 || W > 16384 || H > 16384 ||
+      (uint64_t)n_cams * W * H > (1ull << 31))
+    return fail(VRN_ERR_INVALID_ARG, "n_cams must be 1..16 and W, H 1..16384 (at most 2^31 pixels)");
+  vrn_status st = check_opts(opts);
+  if (st != VRN_OK) return st;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (!find_field(ctx, field)) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  // every path writes the same outputs: RGBA float4 and a uint32 count per pixel
+  *out = (uint64_t)kWsBytes + (uint64_t)n_cams * W * H * (4 * sizeof(float) + sizeof(uint32_t));
   return VRN_OK;
 }
 
@@ -734,7 +768,7 @@ vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_
   if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
   hipSetDevice(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_prune(f->dev, alpha, points_per_voxel, (int)compute, d_bits_out, d_max_opacity, s);
+  hipError_t e = launch_prune(f->dev, alpha, points_per_voxel, (int)compute, d_bits_out, d_max_opacity, ctx->n_cu, s);
   if (e != hipSuccess) return hip_fail(e, "prune");
   track(f, s);
   return VRN_OK;

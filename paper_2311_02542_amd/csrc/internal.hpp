@@ -72,6 +72,10 @@ struct FieldDev {
   float lod_c2;              // ln(2 s): LOD constant when the footprint is already normalised
   uint32_t d1_ksteps;        // FP32 k-steps of the first density layer
   uint32_t c1_ksteps;        // FP32 k-steps of the first color layer
+  // grid pruning: the non-empty bricks, listed on the device by each
+  // vrn_prune_grid call ([Gb^3] entries, count in its own 256-byte block)
+  uint32_t* brick_list;
+  uint32_t* brick_count;
 };
 
 // Workspace layout (bytes).  Counters are spaced 64 B apart.
@@ -133,7 +137,7 @@ hipError_t launch_march(const FieldDev& F, const vrn_camera* d_cams, uint32_t n_
 hipError_t launch_encode(const FieldDev& F, const float* xyz, const float* t, const float* r,
                          uint32_t n, float* feat, hipStream_t s);
 hipError_t launch_prune(const FieldDev& F, float alpha, uint32_t npts, int compute, uint32_t* bits_out,
-                        float* max_op, hipStream_t s);
+                        float* max_op, int n_cu, hipStream_t s);
 hipError_t launch_set_occupancy(const FieldDev& F, const uint32_t* bits, hipStream_t s);
 hipError_t launch_mlp(const FieldDev& F, const float* feat, const float* dir, uint32_t n,
                       int compute, float* sigma, float* rgb, hipStream_t s);

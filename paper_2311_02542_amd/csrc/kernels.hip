@@ -483,7 +483,16 @@ __global__ __launch_bounds__(kBlock) void mlp_kernel(FieldDev F, const float* fe
 
 // ---------------------------------------------------------------------------
 // grid pruning (Sec. 4.3, App. C): max opacity over points inside each
-// occupied voxel, threshold alpha; pruning only clears bits
+// occupied voxel, threshold alpha; pruning only clears bits.
+//
+// Three launches: (1) the output bits start as the field's occupancy (and
+// the maximum opacity of every unoccupied voxel as NaN); (2) the non-empty
+// 4x4x4 bricks are listed; (3) persistent waves walk that list (wave w takes
+// entries w, w + n_waves, ...), queue each brick's occupied voxels in LDS,
+// and evaluate them 64 voxels at a time -- 16-sample MFMA tiles of the
+// voxels' points through the same encode and density layers as the
+// renderer -- then clear the bits of voxels below alpha.  Only occupied
+// voxels cost work, and the weights are staged once per resident block.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ bool cell_occupied(const FieldDev& F, uint32_t x, uint32_t y, uint32_t z) {
@@ -504,68 +513,215 @@ __device__ __forceinline__ float voxel_offset(uint32_t npts, uint32_t p, uint32_
   return ((float)c + 0.5f) / (float)p;
 }
 
-template <bool TAB16, int MODE>
-__global__ __launch_bounds__(kBlock) void prune_kernel(FieldDev F, float alpha, uint32_t npts, uint32_t p,
-                                                      uint32_t* bits_out, float* max_op) {
-  __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
-  __shared__ float s_b[kBiasTotal];
-  __shared__ LevelDev s_lv[kMaxLevels];
-  __shared__ uint32_t s_max[kBlock];
-  __shared__ uint32_t s_slot[kBlock];
-  load_weights<MODE>(F, s_w, s_b);
-  if (threadIdx.x < F.L) s_lv[threadIdx.x] = F.levels[threadIdx.x];
-  s_max[threadIdx.x] = 0u;
-  __syncthreads();
-  const __amdgpu_buffer_rsrc_t tab = table_rsrc(F);
-  const int lane = lane_id(), g = lane >> 4;
-  const int wave_base = (threadIdx.x >> 6) << 6;
-  const uint64_t n = (uint64_t)F.G * F.G * F.G;
-  const uint64_t chunk = blockIdx.x * (uint64_t)(kBlock / 64) + threadIdx.x / 64;
-  const uint64_t v = chunk * 64 + (uint64_t)lane;
+// (1) one thread per 32-bit output word (G^3 < 2^31, so 32-bit indices)
+__global__ void prune_init_kernel(FieldDev F, uint32_t* bits_out, float* max_op) {
   const uint32_t G = F.G;
-  const uint32_t vx = (uint32_t)(v % G), vy = (uint32_t)((v / G) % G), vz = (uint32_t)(v / ((uint64_t)G * G));
-  const bool occ = v < n && cell_occupied(F, vx, vy, vz);
-  const uint64_t m = __ballot(occ);
-  const int nv = __popcll(m);
-  const int rank = __popcll(m & ((1ull << lane) - 1ull));
-  if (occ) s_slot[wave_base + rank] = (uint32_t)lane;
-  __builtin_amdgcn_wave_barrier();
-  const int ns = nv * (int)npts;
-  const float cell = F.inv_cs;
-  for (int t = 0; t * 16 < ns; ++t) {
-    asm volatile("" ::: "memory");
-    const int s = t * 16 + (lane & 15);
-    const bool act = s < ns;
-    const int vr = act ? s / (int)npts : 0;
-    const uint32_t pi = act ? (uint32_t)(s % (int)npts) : 0u;
-    const int src = act ? (int)s_slot[wave_base + vr] : lane;
-    const uint64_t sv = chunk * 64 + (uint64_t)src;
-    const uint32_t c[3] = {(uint32_t)(sv % G), (uint32_t)((sv / G) % G), (uint32_t)(sv / ((uint64_t)G * G))};
-    float x[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = F.amin[a] + ((float)c[a] + voxel_offset(npts, p, pi, a)) * cell;
-    float feat[8];
-    uint32_t fetches = 0;
-    // every level weighs 1 (no ray, no LOD): L* above the finest level
-    encode_point<TAB16, MODE == 0>(F, s_lv, tab, x, 1.0e9f, act, g, feat, fetches);
-    float shs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    float o0, lg[3];
-    run_mlp<MODE>(s_w, s_b, F, feat, shs, lane, o0, lg);
-    if (act && g == 0) {
-      const float op = 1.0f - expf(-expf(o0) * F.dt);
-      atomicMax(&s_max[wave_base + vr], __float_as_uint(fmaxf(op, 0.0f)));
+  const uint32_t n = G * G * G;
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (n + 31u) / 32u) return;
+  const uint32_t i0 = w * 32u;
+  uint32_t x = i0 % G, y = (i0 / G) % G, z = i0 / (G * G);
+  uint32_t out = 0u;
+  for (uint32_t j = 0; j < 32u && i0 + j < n; ++j) {
+    if (cell_occupied(F, x, y, z)) out |= 1u << j;
+    else if (max_op) max_op[i0 + j] = __builtin_nanf("");
+    if (++x == G) {
+      x = 0;
+      if (++y == G) {
+        y = 0;
+        ++z;
+      }
     }
   }
-  __builtin_amdgcn_wave_barrier();
-  float mx = 0.0f;
-  if (occ) mx = __uint_as_float(s_max[wave_base + rank]);
-  const bool keep = occ && mx >= alpha;
-  const uint64_t km = __ballot(keep);
-  if (max_op && v < n) max_op[v] = occ ? mx : __builtin_nanf("");
-  if (lane == 0) {
-    const uint64_t words = (n + 31) / 32;
-    if (2 * chunk < words) bits_out[2 * chunk] = (uint32_t)km;
-    if (2 * chunk + 1 < words) bits_out[2 * chunk + 1] = (uint32_t)(km >> 32);
+  bits_out[w] = out;
+}
+
+// (2) indices of the non-empty bricks, in any order (count zeroed before)
+__global__ void brick_list_kernel(FieldDev F, uint32_t* list, uint32_t* count) {
+  const uint32_t nb = F.Gb * F.Gb * F.Gb;
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool nz = b < nb && F.bricks[b] != 0ull;
+  const uint64_t m = __ballot(nz);
+  if (m == 0) return;
+  const int lane = lane_id();
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = (uint32_t)shfl_i((int)base, leader);
+  if (nz) list[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = b;
+}
+
+// Density layers only (the pruning pass needs sigma, not color), in the
+// renderer's fragment layout.  Lanes 0..15 return the density pre-activation
+// o0 of samples 0..15.
+__device__ __forceinline__ float density_tile_f32(const float4* __restrict__ sw, const float* __restrict__ sb,
+                                                  uint32_t d1_groups, const float feat[8], int lane) {
+  const int g = lane >> 4;
+  v4f h[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) h[ot] = bias_acc(sb, kB1 + 16 * ot, g);
+#pragma unroll
+  for (int s4 = 0; s4 < 2; ++s4) {
+    if ((uint32_t)s4 < d1_groups) {
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        const float4 w = sw[kW32_D1 / 4 + (ot * 2 + s4) * 64 + lane];
+        h[ot] = mfma_f32(w.x, feat[4 * s4 + 0], h[ot]);
+        h[ot] = mfma_f32(w.y, feat[4 * s4 + 1], h[ot]);
+        h[ot] = mfma_f32(w.z, feat[4 * s4 + 2], h[ot]);
+        h[ot] = mfma_f32(w.w, feat[4 * s4 + 3], h[ot]);
+      }
+    }
+  }
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) h[ot] = relu4(h[ot]);
+  v4f o = zero4();
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const float4 w = sw[kW32_D2 / 4 + it * 64 + lane];
+    o = mfma_f32(w.x, h[it][0], o);
+    o = mfma_f32(w.y, h[it][1], o);
+    o = mfma_f32(w.z, h[it][2], o);
+    o = mfma_f32(w.w, h[it][3], o);
+  }
+  return o[0] + sb[kB2 + 4 * g];
+}
+
+template <bool BF>
+__device__ __forceinline__ float density_tile_16(const uint4* __restrict__ sw, const float* __restrict__ sb,
+                                                 const float feat[8], int lane) {
+  typedef Half8<BF> H;
+  typedef typename H::vec vec;
+  const int g = lane >> 4;
+  auto wfrag = [&](int off16, int idx) -> vec {
+    const uint4 u = sw[off16 / 8 + idx * 64 + lane];
+    vec v;
+    __builtin_memcpy(&v, &u, 16);
+    return v;
+  };
+  const vec xin = H::pack(feat);
+  vec hp[2];
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    const v4f a = H::mfma(wfrag(kW16_D1, 2 * pair), xin, bias_acc(sb, kB1 + 32 * pair, g));
+    const v4f b = H::mfma(wfrag(kW16_D1, 2 * pair + 1), xin, bias_acc(sb, kB1 + 32 * pair + 16, g));
+    const float hv[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    hp[pair] = H::relu_pack(hv);
+  }
+  const v4f o = H::mfma(wfrag(kW16_D2, 1), hp[1], H::mfma(wfrag(kW16_D2, 0), hp[0], bias_acc(sb, kB2, g)));
+  return o[0];
+}
+
+// The density-layer weights (D1 and D2) are the first kW32_C1 / kW16_C1
+// elements of each weight form.
+template <int MODE>
+struct DensitySmem {
+  static constexpr int kBytes = (MODE == 0) ? kW32_C1 * 4 : kW16_C1 * 2;
+};
+
+constexpr int kPruneQueue = 128;   // per-wave voxel queue: < 64 carried + one brick
+
+// (3) persistent pruning waves over the brick list.  TET: 4 points per voxel.
+template <bool TAB16, int MODE, bool TET>
+__global__ __launch_bounds__(kBlock) void prune_kernel(FieldDev F, float alpha, uint32_t npts, uint32_t p,
+                                                      const uint32_t* list, const uint32_t* count,
+                                                      uint32_t* bits_out, float* max_op) {
+  __shared__ __align__(16) uint8_t s_w[DensitySmem<MODE>::kBytes];
+  __shared__ float s_b[kBiasTotal];
+  __shared__ LevelDev s_lv[kMaxLevels];
+  __shared__ uint32_t s_q[kBlock / 64][kPruneQueue];
+  __shared__ uint32_t s_max[kBlock / 64][64];
+  {
+    const uint4* src = weight_src<MODE>(F);
+    uint4* dst = reinterpret_cast<uint4*>(s_w);
+    for (int i = threadIdx.x; i < DensitySmem<MODE>::kBytes / 16; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < kBiasTotal; i += blockDim.x) s_b[i] = F.bias[i];
+    if (threadIdx.x < F.L) s_lv[threadIdx.x] = F.levels[threadIdx.x];
+  }
+  __syncthreads();
+  const __amdgpu_buffer_rsrc_t tab = table_rsrc(F);
+  const int lane = lane_id(), g = lane >> 4, wv = threadIdx.x >> 6;
+  uint32_t* q = s_q[wv];
+  uint32_t* mx = s_max[wv];
+  const uint32_t n_list = *count;
+  const uint32_t n_waves = gridDim.x * (kBlock / 64);
+  const uint32_t G = F.G, Gb = F.Gb;
+  const float cell = F.inv_cs;
+  int qn = 0;
+  for (uint32_t i = blockIdx.x * (kBlock / 64) + (uint32_t)wv;; i += n_waves) {
+    const bool more = i < n_list;
+    if (more) {
+      // queue the occupied voxels of one brick, packed x | y << 10 | z << 20
+      const uint32_t b = list[i];
+      const unsigned long long w = F.bricks[b];
+      const uint32_t bx = b % Gb, by = (b / Gb) % Gb, bz = b / (Gb * Gb);
+      if ((w >> lane) & 1ull) {
+        const int rank = __popcll(w & ((1ull << lane) - 1ull));
+        const uint32_t x = 4u * bx + ((uint32_t)lane & 3u), y = 4u * by + (((uint32_t)lane >> 2) & 3u),
+                       z = 4u * bz + ((uint32_t)lane >> 4);
+        q[qn + rank] = x | (y << 10) | (z << 20);
+      }
+      qn += __popcll(w);
+    }
+    __builtin_amdgcn_wave_barrier();
+    while (qn >= 64 || (!more && qn > 0)) {
+      asm volatile("" ::: "memory");
+      const int V = qn < 64 ? qn : 64;
+      mx[lane] = 0u;
+      __builtin_amdgcn_wave_barrier();
+      const int ns = V * (int)npts;
+      for (int t = 0; t * 16 < ns; ++t) {
+        asm volatile("" ::: "memory");
+        const int s = t * 16 + (lane & 15);
+        const bool act = s < ns;
+        int vr = 0;
+        uint32_t pi = 0;
+        if (act) {
+          if constexpr (TET) {
+            vr = s >> 2;
+            pi = (uint32_t)s & 3u;
+          } else {
+            vr = s / (int)npts;
+            pi = (uint32_t)(s - vr * (int)npts);
+          }
+        }
+        const uint32_t c = q[vr];
+        const uint32_t cc[3] = {c & 1023u, (c >> 10) & 1023u, c >> 20};
+        float x[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = F.amin[a] + ((float)cc[a] + voxel_offset(npts, p, pi, a)) * cell;
+        float feat[8];
+        uint32_t fetches = 0;
+        // every level weighs 1 (no ray, no LOD): L* above the finest level
+        encode_point<TAB16, MODE == 0>(F, s_lv, tab, x, 1.0e9f, act, g, feat, fetches);
+        float o0;
+        if constexpr (MODE == 0)
+          o0 = density_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, lane);
+        else
+          o0 = density_tile_16<MODE == 2>(reinterpret_cast<const uint4*>(s_w), s_b, feat, lane);
+        if (act && g == 0) {
+          float op = 1.0f - expf(-expf(o0) * F.dt);
+          // a NaN opacity (16-bit activations that overflowed) keeps the voxel
+          if (!(op == op)) op = 1.0f;
+          atomicMax(&mx[vr], __float_as_uint(fmaxf(op, 0.0f)));
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (lane < V) {
+        const uint32_t c = q[lane];
+        const uint32_t idx = (c & 1023u) + G * (((c >> 10) & 1023u) + G * (c >> 20));
+        const float m = __uint_as_float(mx[lane]);
+        if (!(m >= alpha)) atomicAnd(&bits_out[idx >> 5], ~(1u << (idx & 31u)));
+        if (max_op) max_op[idx] = m;
+      }
+      // drop the V evaluated voxels from the front of the queue
+      const uint32_t tail = lane + V < qn ? q[lane + V] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (lane + V < qn) q[lane] = tail;
+      __builtin_amdgcn_wave_barrier();
+      qn -= V;
+    }
+    if (!more) break;
   }
 }
 
@@ -682,21 +838,49 @@ hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t
   return hipGetLastError();
 }
 
+template <bool TAB16, int MODE, bool TET>
+static void launch_prune_impl(const FieldDev& F, float alpha, uint32_t npts, uint32_t p, const uint32_t* list,
+                              const uint32_t* count, uint32_t* bits_out, float* max_op, int n_cu, hipStream_t s) {
+  static int per_cu = -1;
+  if (per_cu < 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, prune_kernel<TAB16, MODE, TET>, kBlock, 0) !=
+            hipSuccess || nb < 1)
+      nb = 1;
+    per_cu = nb;
+  }
+  hipLaunchKernelGGL((prune_kernel<TAB16, MODE, TET>), dim3((unsigned)(per_cu * n_cu)), dim3(kBlock), 0, s, F,
+                     alpha, npts, p, list, count, bits_out, max_op);
+}
+
+template <bool TAB16, int MODE>
+static void launch_prune_mode(const FieldDev& F, float alpha, uint32_t npts, uint32_t p, const uint32_t* list,
+                              const uint32_t* count, uint32_t* bits_out, float* max_op, int n_cu, hipStream_t s) {
+  if (npts == 4) launch_prune_impl<TAB16, MODE, true>(F, alpha, npts, p, list, count, bits_out, max_op, n_cu, s);
+  else launch_prune_impl<TAB16, MODE, false>(F, alpha, npts, p, list, count, bits_out, max_op, n_cu, s);
+}
+
 hipError_t launch_prune(const FieldDev& F, float alpha, uint32_t npts, int compute, uint32_t* bits_out,
-                        float* max_op, hipStream_t s) {
+                        float* max_op, int n_cu, hipStream_t s) {
   uint32_t p = 1;
   while ((p + 1) * (p + 1) * (p + 1) <= npts) ++p;
-  const uint64_t n = (uint64_t)F.G * F.G * F.G;
-  const uint64_t waves = (n + 63) / 64;
-  const dim3 gr((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64))), bl(kBlock);
+  const uint32_t n = F.G * F.G * F.G;
+  const uint32_t words = (n + 31u) / 32u;
+  hipLaunchKernelGGL(prune_init_kernel, dim3((words + 255u) / 256u), dim3(256), 0, s, F, bits_out, max_op);
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, F.brick_count, (uint64_t)1);
+  const uint32_t nb = F.Gb * F.Gb * F.Gb;
+  hipLaunchKernelGGL(brick_list_kernel, dim3((nb + 255u) / 256u), dim3(256), 0, s, F, F.brick_list,
+                     F.brick_count);
+  const uint32_t* list = F.brick_list;
+  const uint32_t* cnt = F.brick_count;
   if (F.table_f16) {
-    if (compute == 0) hipLaunchKernelGGL((prune_kernel<true, 0>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
-    else if (compute == 1) hipLaunchKernelGGL((prune_kernel<true, 1>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
-    else hipLaunchKernelGGL((prune_kernel<true, 2>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+    if (compute == 0) launch_prune_mode<true, 0>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
+    else if (compute == 1) launch_prune_mode<true, 1>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
+    else launch_prune_mode<true, 2>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
   } else {
-    if (compute == 0) hipLaunchKernelGGL((prune_kernel<false, 0>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
-    else if (compute == 1) hipLaunchKernelGGL((prune_kernel<false, 1>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
-    else hipLaunchKernelGGL((prune_kernel<false, 2>), gr, bl, 0, s, F, alpha, npts, p, bits_out, max_op);
+    if (compute == 0) launch_prune_mode<false, 0>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
+    else if (compute == 1) launch_prune_mode<false, 1>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
+    else launch_prune_mode<false, 2>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
   }
   return hipGetLastError();
 }

@@ -1,8 +1,11 @@
 """Serving systems tests: HIP graph replay equals eager launches (several
 replays with eager work and synchronisation in between), a request gives the
 same result alone and inside a concurrent mix (bitwise: every ray's
-arithmetic is independent of batch composition), HBM-budget admission and
-queueing, and unload of a busy field."""
+arithmetic is independent of batch composition), served results of all
+three resident scenes held to the FP64 oracle, HBM-budget admission and
+queueing (held results count against the budget), timeouts and
+cancellation, and unload of a busy field."""
+import threading
 import time
 
 import numpy as np
@@ -49,12 +52,12 @@ def test_graph_replay_equals_eager():
 
 
 def _fields():
-    return {"A": synth.field_blobs64(), "B": synth.field_blobs_3m2()}
+    return synth.fields_serving()
 
 
 def test_alone_vs_mix_bitwise():
     torch = need_gpu()
-    srv = serve.Server(_fields(), 4 << 30, n_slots=3, compute="f16", use_graphs=True)
+    srv = serve.Server(_fields(), 8 << 30, n_slots=3, compute="f16", use_graphs=True)
     probe = synth.request_cameras("A", "tile", 1234)
     srv.start()
     alone = srv.submit("A", *probe)
@@ -65,7 +68,7 @@ def test_alone_vs_mix_bitwise():
     mix = []
     rng = np.random.default_rng(0)
     for i in range(24):
-        scene = "AB"[i % 2]
+        scene = "ABC"[i % 3]
         kind = ["preview", "tile", "stereo"][rng.integers(3)]
         cams, W, H = synth.request_cameras(scene, kind, int(rng.integers(1 << 30)))
         mix.append(srv.submit(scene, cams, W, H))
@@ -97,16 +100,22 @@ def test_admission_budget_and_queueing():
     srv = serve.Server(fields, budget, n_slots=2, compute="f16", use_graphs=False)
     with pytest.raises(serve.ServeError):
         srv.submit("A", *synth.request_cameras("A", "stereo", 1))     # 2x2048^2 can never fit
+    assert srv.out_bytes(1, 1024, 1024) == 1024 * 1024 * 20
     srv.start()
     reqs = [srv.submit("A", *synth.request_cameras("A", "tile", 100 + i)) for i in range(4)]
-    srv.stop(drain=True)
-    assert all(r.done.is_set() for r in reqs)
     R = capi.Renderer(0)
     fid = R.load(fields["A"])
+    # each result holds the only buffer until it is released: the next request
+    # waits for the release instead of failing
     for r in reqs:
+        assert r.done.wait(30) and r.error is None
         ref, _ = R.render(fid, r.cams, r.W, r.H, "f16")
         torch.cuda.synchronize()
         assert torch.equal(ref, r.result[0])
+        assert srv._used_bytes() <= budget
+        r.release()
+        assert r.result is None
+    srv.stop(drain=True)
     R.unload(fid)
     R.close()
     srv.close()
@@ -169,12 +178,12 @@ def test_warmup_captures_buckets_and_serves_exactly():
     srv = serve.Server(_fields(), 4 << 30, n_slots=2, compute="f16", use_graphs=True)
     shapes = [(256, 256, 1), (256, 256, 2)]
     srv.warmup(shapes)
-    keys = {k for s in srv.slots for k in s.buckets}
-    assert keys == {(sc, w, h, n, "f16") for sc in ("A", "B") for (w, h, n) in shapes}
+    keys = {k for s in srv.slots for k in s.rings}
+    assert keys == {(sc, w, h, n, "f16") for sc in ("A", "B", "C") for (w, h, n) in shapes}
     srv.start()
-    reqs = [srv.submit(sc, *synth.request_cameras(sc, "preview", 50 + i)) for i, sc in enumerate("ABAB")]
+    reqs = [srv.submit(sc, *synth.request_cameras(sc, "preview", 50 + i)) for i, sc in enumerate("ABCA")]
     srv.stop(drain=True)
-    assert {k for s in srv.slots for k in s.buckets} == keys
+    assert {k for s in srv.slots for k in s.rings} == keys
     R = capi.Renderer(0)
     fids = {name: R.load(f) for name, f in _fields().items()}
     for r in reqs:
@@ -185,4 +194,125 @@ def test_warmup_captures_buckets_and_serves_exactly():
     for fid in fids.values():
         R.unload(fid)
     R.close()
+    srv.close()
+
+
+def _served_vs_oracle(r, field, n_px, rng):
+    """Max/mean abs PQ error of a served request on sampled pixels vs the FP64 oracle."""
+    from oracle.render import render_fp64
+    rgba = r.result[0].cpu().numpy().reshape(-1, 4).astype(np.float64)
+    n_cams = len(r.cams)
+    px = np.stack([rng.integers(0, n_cams, n_px), rng.integers(0, r.H, n_px), rng.integers(0, r.W, n_px)], 1)
+    ref = render_fp64(field, r.cams, r.W, r.H, pixels=px)
+    g = rgba[(px[:, 0] * r.H + px[:, 1]) * r.W + px[:, 2]]
+    return np.abs(g[:, :3] - ref["rgba"][:, :3]), ref["rgba"][:, 3]
+
+
+def test_served_results_match_oracle_all_scenes():
+    """A mixed burst over all three resident scenes (the 64^2-blob field with
+    FP32 tables, the 3.2 m blob field with FP16 tables, and the 2^20-entry
+    FP16 room), served by the FP16 path with batching and graphs: sampled
+    pixels of every served request are within the FP16 budget fixed in
+    advance (mean <= 1/4095, max <= 1/1023 PQ) of the FP64 oracle."""
+    torch = need_gpu()
+    fields = synth.fields_serving()
+    srv = serve.Server(fields, 24 << 30, n_slots=4, compute="f16", use_graphs=True)
+    srv.warmup([(256, 256, 1), (256, 256, 2), (1024, 1024, 1), (2048, 2048, 2)])
+    srv.start()
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(18):
+        scene = "ABC"[i % 3]
+        kind = ["preview", "tile", "stereo"][(i // 3) % 3]
+        reqs.append(srv.submit(scene, *synth.request_cameras(scene, kind, int(rng.integers(1 << 30)))))
+    srv.stop(drain=True)
+    torch.cuda.synchronize()
+    errs, alphas = {s: [] for s in "ABC"}, {s: [] for s in "ABC"}
+    for r in reqs:
+        assert r.done.is_set() and r.error is None, r.error
+        e, a = _served_vs_oracle(r, fields[r.scene], 48, rng)
+        errs[r.scene].append(e)
+        alphas[r.scene].append(a)
+        r.release()
+    for s in "ABC":
+        e = np.concatenate(errs[s])
+        a = np.concatenate(alphas[s])
+        print(f"scene {s}: {e.shape[0]} px, max {e.max():.2e} mean {e.mean():.2e}, "
+              f"content {np.mean(a > 0.5):.2f}")
+        assert np.mean(a > 0.5) > 0.1, f"scene {s}: sampled pixels hold almost no content"
+        assert e.max() <= 1 / 1023 and e.mean() <= 1 / 4095, f"scene {s} outside the FP16 budget"
+    assert srv.held_bytes() == 0
+    srv.close()
+
+
+def test_timeout_and_cancel():
+    torch = need_gpu()
+    srv = serve.Server({"A": synth.field_blobs64()}, 4 << 30, n_slots=1, compute="f16", use_graphs=False)
+    # queued past their deadline, or cancelled while queued: never launched
+    late = srv.submit("A", *synth.request_cameras("A", "preview", 1), timeout_s=1e-4)
+    ok = srv.submit("A", *synth.request_cameras("A", "preview", 2), timeout_s=60)
+    gone = srv.submit("A", *synth.request_cameras("A", "preview", 3))
+    assert gone.cancel()
+    time.sleep(0.01)
+    srv.start()
+    srv.stop(drain=True)
+    assert isinstance(late.error, serve.ServeTimeout) and late.t_start is None and late.result is None
+    assert isinstance(gone.error, serve.ServeCancelled) and gone.t_start is None and gone.result is None
+    assert ok.error is None and ok.result is not None
+    assert not ok.cancel()                  # done: nothing to cancel
+    ok.release()
+    # cancelled or timed out around launch: whichever way it goes, the result is
+    # discarded and its buffer returned to the ring
+    srv.start()
+    big = srv.submit("A", *synth.request_cameras("A", "stereo", 4))
+    cancelled = big.cancel()
+    fast = srv.submit("A", *synth.request_cameras("A", "stereo", 5), timeout_s=1e-6)
+    srv.stop(drain=True)
+    torch.cuda.synchronize()
+    if cancelled:
+        assert isinstance(big.error, serve.ServeCancelled) and big.result is None
+    else:                                   # it had already finished: nothing was cancelled
+        assert big.error is None
+        big.release()
+    assert isinstance(fast.error, serve.ServeTimeout) and fast.result is None
+    assert srv.held_bytes() == 0
+    srv.close()
+
+
+def test_held_results_count_against_budget():
+    """Results handed to clients are ring buffers that count against the HBM
+    budget until released: device memory of the server stays within the
+    budget during a burst whose results are all kept."""
+    torch = need_gpu()
+    fields = {"A": synth.field_blobs64()}
+    fbytes = synth.field_bytes(fields["A"])
+    one = 1024 * 1024 * 20
+    budget = fbytes * 2 + (1 << 20) + 2 * one + (1 << 20)      # two 1024^2 buffers
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    srv = serve.Server(fields, budget, n_slots=2, compute="f16", use_graphs=False)
+    srv.start()
+    reqs = [srv.submit("A", *synth.request_cameras("A", "tile", 300 + i)) for i in range(5)]
+    assert reqs[0].done.wait(30) and reqs[1].done.wait(30)
+    time.sleep(0.05)
+    # two results held: the others wait for a release
+    assert sum(r.done.is_set() for r in reqs) == 2
+    assert srv.held_bytes() == 2 * one
+    assert srv._used_bytes() <= budget
+    released = threading.Event()
+
+    def consumer():
+        for r in reqs:
+            assert r.done.wait(30) and r.error is None
+            r.release()
+        released.set()
+
+    th = threading.Thread(target=consumer)
+    th.start()
+    th.join(60)
+    assert released.is_set()
+    srv.stop(drain=True)
+    peak = torch.cuda.max_memory_allocated() - base
+    assert peak <= budget - srv.field_bytes, (peak, budget - srv.field_bytes)
     srv.close()

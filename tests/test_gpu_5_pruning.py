@@ -135,3 +135,29 @@ def test_prune_argument_errors(R):
         with pytest.raises(capi.VrnError):
             capi.vrn_prune_grid(R.ctx, fid, kw["alpha"], bits, None, kw.get("points_per_voxel", 4))
     R.unload(fid)
+
+
+def test_prune_keeps_voxels_whose_fp16_opacity_overflows(R):
+    """First-layer weights of 1e6 on one feature are finite, but do not fit
+    FP16: wherever that feature is positive the FP16 hidden units are
+    infinite, and density-output weights of both signs (+1 and -0.5, summing
+    to +16) turn them into a NaN density.  In FP32 the same points have a
+    huge positive density and opacity 1.  A NaN opacity must keep its voxel
+    (pruning may only drop what it has shown to be transparent): every voxel
+    the FP32 pass finds saturated is kept by the FP16 pass, with maximum
+    opacity 1."""
+    f = synth.field_blobs64()
+    f["mlp"] = {k: v.copy() for k, v in f["mlp"].items()}
+    f["mlp"]["W1"][0, :] = 1.0e6
+    f["mlp"]["W2"][:, 0] = np.where(np.arange(64) < 32, 1.0, -0.5)
+    fid = R.load(f)
+    bits32, mx32 = _gpu_prune(R, fid, 64, 0.999, 4, "f32")
+    bits16, mx16 = _gpu_prune(R, fid, 64, 0.999, 4, "f16")
+    R.unload(fid)
+    sat = mx32 == 1.0
+    print(f"{int(sat.sum())} saturated voxels of {int(np.isfinite(mx32).sum())} occupied")
+    assert sat.sum() > 1000
+    kept16 = synth.unpack_bits(bits16, 64).ravel()
+    assert kept16[sat].all()
+    assert (mx16[sat] == 1.0).all()
+    assert not np.isnan(mx16[np.isfinite(mx32)]).any()
