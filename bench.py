@@ -58,6 +58,44 @@ def profiled_traffic(path):
     return None
 
 
+def profile_lines(prefix):
+    """`<prefix> <path>: <value>` lines of the committed counter summary, or
+    {} when the kernel sources changed since the counters were taken."""
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return {}
+    if f"source sha256: {source_hash()}" not in txt:
+        return {}
+    out = {}
+    for line in txt.splitlines():
+        if line.startswith(prefix + " "):
+            k, v = line[len(prefix) + 1:].split(":", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def roofline(hr, path):
+    """The dominant kernel against MI355X's HBM peak.  `frac` is effective:
+    algorithmic gather bytes over kernel time (most of them are served by
+    L1, L2 and MALL, not HBM); `hbm_frac` is the counter-measured HBM traffic
+    over the same time; `bound` names the limiter the counters show."""
+    traffic = profiled_traffic(path)
+    ms = hr["ms_per_step"]
+    limiter = profile_lines("limiter").get(path)
+    out = {"bound": limiter.split(";")[0] if limiter else "hbm", "achieved": hr["achieved_GBs"],
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hr["achieved_GBs"] / HBM_PEAK_GBS,
+           "frac_kind": "effective: algorithmic gather bytes / kernel time / HBM peak",
+           "traffic": traffic, "kernel": "render_kernel",
+           "algorithmic_bytes_per_launch": hr["bytes_per_launch"]}
+    if limiter:
+        out["limiter"] = limiter.split(";", 1)[1].strip() if ";" in limiter else limiter
+    if traffic:
+        out["hbm_GBs"] = traffic / (ms * 1e-3) / 1e9
+        out["hbm_frac"] = out["hbm_GBs"] / HBM_PEAK_GBS
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +115,13 @@ def parse():
                          "on the house field (added to the JSON line as `extras`)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain 1 GiB device copy (to scale profiler byte counters)")
+    ap.add_argument("--error-frames", default="0,150,299", help="frames of the path whose PQ error is measured")
+    ap.add_argument("--no-path", action="store_true", help="skip timing every frame of the 300-frame path")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving runs")
+    ap.add_argument("--serve-rates", default="500,1000,1800",
+                    help="offered loads of the serving runs, requests per second (fixed, not relative)")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--no-c3", action="store_true", help="with --extras: skip the 32-pose precision report")
     return ap.parse_args()
 
 
@@ -241,20 +286,138 @@ def time_extras(R, house16):
     return out
 
 
-def pq_error(R, fid, field_ref, cams, W, H, compute, n_px, seed=0):
-    """Max / mean abs PQ error and PSNR of a path vs the FP64 oracle on sampled pixels."""
+def _err_stats(err):
+    mse = float(np.mean(err ** 2)) if err.size else 0.0
+    return {"max_abs": float(err.max(initial=0.0)), "mean_abs": float(err.mean()) if err.size else 0.0,
+            "psnr_pq": float(10 * math.log10(1.0 / max(mse, 1e-30)))}
+
+
+def pq_error(R, fid, field_ref, frames, frame_ids, W, H, compute, n_px, seed=0):
+    """Max / mean abs PQ error and PSNR of a path vs the FP64 oracle on n_px
+    sampled pixels (both eyes) of each of the given frames of the path, per
+    frame and over all of them; `content` is the fraction of sampled pixels
+    whose oracle alpha exceeds 0.5."""
     import torch
     from oracle.render import render_fp64
-    rgba, ns = R.render(fid, cams, W, H, compute)
-    torch.cuda.synchronize()
     rng = np.random.default_rng(seed)
-    px = np.stack([rng.integers(0, len(cams), n_px), rng.integers(0, H, n_px), rng.integers(0, W, n_px)], 1)
-    ref = render_fp64(field_ref, cams, W, H, pixels=px)
-    g = rgba.cpu().numpy().reshape(-1, 4)[(px[:, 0] * H + px[:, 1]) * W + px[:, 2]].astype(np.float64)
-    err = np.abs(g[:, :3] - ref["rgba"][:, :3])
-    mse = float(np.mean(err ** 2))
-    return {"max_abs": float(err.max()), "mean_abs": float(err.mean()),
-            "psnr_pq": float(10 * math.log10(1.0 / max(mse, 1e-30))), "pixels": int(n_px)}
+    per, errs = {}, []
+    for fi in frame_ids:
+        cams = frames[fi]
+        rgba, ns = R.render(fid, cams, W, H, compute)
+        torch.cuda.synchronize()
+        px = np.stack([rng.integers(0, len(cams), n_px), rng.integers(0, H, n_px), rng.integers(0, W, n_px)], 1)
+        ref = render_fp64(field_ref, cams, W, H, pixels=px)
+        g = rgba.cpu().numpy().reshape(-1, 4)[(px[:, 0] * H + px[:, 1]) * W + px[:, 2]].astype(np.float64)
+        err = np.abs(g[:, :3] - ref["rgba"][:, :3])
+        errs.append(err)
+        per[str(fi)] = dict(_err_stats(err), pixels=int(n_px), content=float(np.mean(ref["rgba"][:, 3] > 0.5)))
+        del rgba, ns
+    out = dict(_err_stats(np.concatenate(errs)), pixels=int(n_px * len(frame_ids)),
+               frames=[int(f) for f in frame_ids])
+    out["per_frame"] = per
+    return out
+
+
+def path_latency(R, fid, frames, W, H, compute, warmup):
+    """Every frame of the path rendered once, each timed with HIP events on
+    the launch stream: frame-time percentiles over the whole path."""
+    r = time_path(R, fid, frames, W, H, compute, len(frames), warmup)
+    lat = r["lat_ms"]
+    p99 = float(np.percentile(lat, 99))
+    return {"frames": len(frames), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": p99,
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "fps_at_p99": 1000.0 / p99,
+            "rays_per_s": 2 * W * H * len(frames) / (float(lat.sum()) * 1e-3),
+            "samples_per_s": r["stats"]["samples"] / (float(lat.sum()) * 1e-3)}
+
+
+_C3_FIELD = None
+
+
+def _c3_init(field):
+    global _C3_FIELD
+    _C3_FIELD = field
+
+
+def _c3_oracle(job):
+    """One pose's oracle crop (spawned worker, one BLAS thread)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.render import all_pixels, render_fp64
+    cam, W, H, r0, c0, n = job
+    px = all_pixels(1, W, H, rows=np.arange(r0, r0 + n), cols=np.arange(c0, c0 + n))
+    with threadpool_limits(1):
+        return render_fp64(_C3_FIELD, [cam], W, H, pixels=px)["rgba"]
+
+
+def precision_c3(R, crop=256, workers=16):
+    """The precision workload: the 3.2 m blob field at a 2048^2 eye along its
+    32-pose walk, FP16 tables with FP16 and with BF16 MLPs, against the FP32
+    GPU path (whole image) and the FP64 oracle on a crop x crop window per
+    pose chosen by content (the window with the largest mean alpha: the
+    central window of many poses holds no occupied sample).  Poses whose
+    image has no content are counted and left out of the error figures."""
+    import multiprocessing
+    import torch
+    from paper_2311_02542_amd import synth
+    f32 = synth.field_blobs_3m2(table_dtype=np.float32)
+    f16 = synth.field_blobs_3m2()
+    cams = synth.cameras_walk_3m2(32)
+    W = H = 2048
+    fid32, fid16 = R.load(f32), R.load(f16)
+    poses, jobs, crops = [], [], []
+    for pi, cam in enumerate(cams):
+        g32, _ = R.render(fid32, [cam], W, H, "f32")
+        imgs = {p: R.render(fid16, [cam], W, H, p)[0] for p in ("f16", "bf16")}
+        a = g32[0, :, :, 3]
+        content = float((a > 0.5).float().mean())
+        win = torch.nn.functional.avg_pool2d(a[None, None].double(), crop, stride=16)[0, 0]
+        k = int(torch.argmax(win))
+        r0, c0 = (k // win.shape[1]) * 16, (k % win.shape[1]) * 16
+        rec = {"pose": pi, "content": content, "crop": [int(r0), int(c0), crop],
+               "crop_alpha": float(win.max())}
+        for p, im in imgs.items():
+            e = (im[0, :, :, :3] - g32[0, :, :, :3]).abs().double()
+            mse = float((e ** 2).mean())
+            rec[f"{p}_vs_gpu_f32"] = {"max_abs": float(e.max()), "mean_abs": float(e.mean()),
+                                      "psnr_pq": 10 * math.log10(1.0 / max(mse, 1e-30))}
+        poses.append(rec)
+        if content >= 1e-3:
+            jobs.append((cam, W, H, int(r0), int(c0), crop))
+            crops.append((pi, {p: im[0, r0:r0 + crop, c0:c0 + crop].reshape(-1, 4).cpu().numpy()
+                               for p, im in list(imgs.items()) + [("f32", g32)]}))
+        del g32, imgs
+    R.unload(fid32)
+    R.unload(fid16)
+    workers = max(1, min(workers, os.cpu_count() or 1, len(jobs)))
+    t0 = time.perf_counter()
+    if jobs:
+        with multiprocessing.get_context("spawn").Pool(workers, initializer=_c3_init, initargs=(f32,)) as pool:
+            refs = pool.map(_c3_oracle, jobs, chunksize=1)
+    else:
+        refs = []
+    dt = time.perf_counter() - t0
+    errs = {p: [] for p in ("f32", "f16", "bf16")}
+    by_pose = {rec["pose"]: rec for rec in poses}
+    for (pi, got), ref in zip(crops, refs):
+        for p, g in got.items():
+            e = np.abs(g[:, :3].astype(np.float64) - ref[:, :3])
+            errs[p].append(e)
+            by_pose[pi][f"{p}_vs_oracle"] = _err_stats(e)
+    out = {"poses": len(poses), "poses_with_content": len(jobs), "empty_poses": len(poses) - len(jobs),
+           "crop": crop, "oracle_pixels": len(jobs) * crop * crop, "oracle_s": dt, "oracle_processes": workers,
+           "per_pose": poses}
+    for p, es in errs.items():
+        if es:
+            out[f"{p}_vs_oracle"] = _err_stats(np.concatenate(es))
+    for p in ("f16", "bf16"):
+        v = [rec[f"{p}_vs_gpu_f32"] for rec in poses if rec["content"] >= 1e-3]
+        if v:
+            out[f"{p}_vs_gpu_f32"] = {"max_abs": max(x["max_abs"] for x in v),
+                                      "mean_abs": float(np.mean([x["mean_abs"] for x in v])),
+                                      "psnr_pq_min": min(x["psnr_pq"] for x in v)}
+    if "f16_vs_oracle" in out:
+        out["f16_meets_budget"] = (out["f16_vs_oracle"]["max_abs"] <= 1 / 1023
+                                   and out["f16_vs_oracle"]["mean_abs"] <= 1 / 4095)
+    return out
 
 
 _ORACLE_FIELD = None
@@ -354,11 +517,17 @@ def main():
             "mfma_TFLOPs": flops / (ms * 1e-3) / 1e12,
         }
         del r
+    plat = {}
+    if not args.no_path:
+        for p in paths:
+            print(f"bench: path latency {p} ({len(frames)} frames)", file=sys.stderr, flush=True)
+            plat[p] = path_latency(R, fids[p], frames, W, H, p, min(args.warmup, 10))
     err = {}
     if not args.no_error:
         print("bench: PQ error vs oracle", file=sys.stderr, flush=True)
+        fids_err = [int(x) for x in args.error_frames.split(",") if x]
         for p in paths:
-            err[p] = pq_error(R, fids[p], field32, frames[0], W, H, p, args.error_pixels)
+            err[p] = pq_error(R, fids[p], field32, frames, fids_err, W, H, p, args.error_pixels)
     head = "f16" if "f16" in results else paths[0]
     budget_ok = None
     if head in err:
@@ -383,9 +552,7 @@ def main():
         "samples_per_s": hr["samples_per_s"], "p50_ms": hr["p50_ms"], "p99_ms": hr["p99_ms"],
         "paths": results, "pq_error": err, "error_budget": {"mean_abs": 1 / 4095, "max_abs": 1 / 1023,
                                                              "head_path_meets": budget_ok},
-        "roofline": {"bound": "hbm", "achieved": hr["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": hr["achieved_GBs"] / HBM_PEAK_GBS, "traffic": profiled_traffic(head),
-                     "kernel": "render_kernel", "algorithmic_bytes_per_launch": hr["bytes_per_launch"]},
+        "roofline": roofline(hr, head),
         "mfma": {"achieved_TFLOPs": hr["mfma_TFLOPs"], "peak_TFLOPs": MFMA_PEAK_TFLOPS[head],
                  "frac": hr["mfma_TFLOPs"] / MFMA_PEAK_TFLOPS[head]},
         "context": "paper: dual 2Kx2K at 36 Hz on a 20x A40 demo machine (~302 Mrays/s aggregate), not comparable",
@@ -402,9 +569,33 @@ def main():
         print(f"bench: {args.shares} row shares of path {head}", file=sys.stderr, flush=True)
         line["row_shares"] = time_shares(R, fids[head], frames, W, H, head, args.shares,
                                          min(args.steps, 20), min(args.warmup, 5))
+    if plat:
+        line["path_latency"] = plat
     if args.extras:
         print("bench: unbounded scene and grid pruning", file=sys.stderr, flush=True)
         line["extras"] = time_extras(R, field16)
+        if not args.no_c3:
+            print("bench: precision report, 32 poses of the 2048^2 eye", file=sys.stderr, flush=True)
+            line["extras"]["precision_blobs_3m2_2048"] = precision_c3(R)
+    for fid in fids.values():
+        R.unload(fid)
+    if not args.no_serving:
+        from paper_2311_02542_amd import serve
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        sv = serve.run_serving(synth.fields_serving(), rates, args.serve_requests,
+                               log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        mid = rates[len(rates) // 2]
+        head_run = sv[f"server_f16_at_{mid:g}"]
+        line["serving"] = {"p50_ms": head_run["p50_ms"], "p99_ms": head_run["p99_ms"],
+                           "rays_per_s": head_run["rays_per_s"], "at_rate_req_per_s": mid,
+                           "baseline_p50_ms": sv[f"baseline_f32_fifo_at_{mid:g}"]["p50_ms"],
+                           "baseline_p99_ms": sv[f"baseline_f32_fifo_at_{mid:g}"]["p99_ms"],
+                           "mix": "40% 256^2, 40% 1024^2, 20% 2x2048^2 stereo; scenes uniform over the "
+                                  "64^2-blob field (FP32 tables), the 3.2 m blob field and the 2^20-entry "
+                                  "room (FP16 tables); Poisson arrivals at fixed rates",
+                           "server": "FP16 MFMA, 4 slots, batching, hipGraph per bucket",
+                           "baseline": "FP32, one request at a time (one-slot FIFO), no graphs, same arrival trace",
+                           "runs": sv}
     if cpu is not None:
         line["cpu_baseline"] = cpu
     R.close()

@@ -53,6 +53,11 @@ def compare_render(gpu_rgba, gpu_n, ref, tol, mask=None):
     want = np.where((tie & (g_n == ref["n_lo"]))[:, None], ref["rgba_lo"],
                     np.where((tie & (g_n == ref["n_hi"]))[:, None], ref["rgba_hi"], ref["rgba"]))
     err = np.abs(g_rgba - want)
+    # a tie pixel stopped strictly between the two ends: compositing only
+    # adds non-negative terms, so every channel lies between its values at
+    # n_lo and n_hi; the error is the distance outside that interval
     mid = tie & (g_n != ref["n_lo"]) & (g_n != ref["n_hi"])
-    err[mid] = np.maximum(err[mid] - 2e-4, 0)
+    lo = np.minimum(ref["rgba_lo"][mid], ref["rgba_hi"][mid])
+    hi = np.maximum(ref["rgba_lo"][mid], ref["rgba_hi"][mid])
+    err[mid] = np.maximum(np.maximum(lo - g_rgba[mid], g_rgba[mid] - hi), 0.0)
     return float(err.max(initial=0.0)), float(err.mean() if err.size else 0.0), int(tie.sum())

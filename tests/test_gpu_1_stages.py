@@ -6,6 +6,7 @@ import math
 import numpy as np
 import pytest
 
+from mlp_bound import mlp16_bounds, mlp16_rgb_rms_bound
 from gpu_common import F32, axis_camera, need_gpu, tiny_field
 from oracle.encoding import encode, level_star, lod_weights
 from oracle.march import dense_masked_march
@@ -178,10 +179,13 @@ def test_encode_parity(R, case):
     assert err.max() <= 1e-6, f"max abs feature error {err.max():.3g}"
 
 
-@pytest.mark.parametrize("compute,tol_rgb,tol_sig", [("f32", 1e-6, 2e-6), ("f16", 5e-3, 5e-2),
-                                                     ("bf16", 3e-2, 3e-1)])
+@pytest.mark.parametrize("compute", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("case", ["blobs64", "room256"])
-def test_mlp_parity(R, case, compute, tol_rgb, tol_sig):
+def test_mlp_parity(R, case, compute):
+    """FP32: sigma within 2e-6 relative, RGB within 1e-6.  FP16 / BF16: per
+    sample, sigma within the a-priori worst-case bound of the 16-bit
+    arithmetic and RGB within six standard deviations of its rounding model
+    (tests/mlp_bound.py, itself checked against a CPU emulation)."""
     torch = R.torch
     f = synth.field_blobs64() if case == "blobs64" else synth.field_room256()
     L = int(f["n_levels"])
@@ -197,11 +201,19 @@ def test_mlp_parity(R, case, compute, tol_rgb, tol_sig):
     torch.cuda.synchronize()
     R.unload(fid)
     s_ref, geo = density_mlp(feats.astype(np.float64), f["mlp"])
-    c_ref = color_mlp(geo, sh_basis(d.astype(np.float64), int(f["sh_bands"])), f["mlp"])
+    sh = sh_basis(d.astype(np.float64), int(f["sh_bands"]))
+    c_ref = color_mlp(geo, sh, f["mlp"])
     s_err = np.abs(sig.cpu().numpy() / s_ref - 1)
     c_err = np.abs(rgb.cpu().numpy() - c_ref)
-    assert s_err.max() <= tol_sig, f"sigma rel err {s_err.max():.3g}"
-    assert c_err.max() <= tol_rgb, f"rgb abs err {c_err.max():.3g}"
+    if compute == "f32":
+        tol_sig, tol_rgb = 2e-6, 1e-6
+    else:
+        tol_sig, _ = mlp16_bounds(feats, sh, f["mlp"], compute)
+        tol_rgb = mlp16_rgb_rms_bound(feats, sh, f["mlp"], compute)
+    print(f"{case} {compute}: sigma err / tol max {np.max(s_err / tol_sig):.3f}, "
+          f"rgb err / tol max {np.max(c_err / tol_rgb):.3f}")
+    assert (s_err <= tol_sig).all(), f"sigma rel err {np.max(s_err / tol_sig):.3g} x tolerance"
+    assert (c_err <= tol_rgb).all(), f"rgb abs err {np.max(c_err / tol_rgb):.3g} x tolerance"
 
 
 def test_march_bit_exact_clear_runs(R):
