@@ -1,5 +1,6 @@
 // C ABI of the renderer (include/vrn.h): host validation, field residency,
 // MFMA weight layout, workspaces and launches.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +19,37 @@ using namespace vrn;
 namespace {
 
 thread_local std::string g_err;
+
+// roctx ranges around the entry points, so a marker trace (rocprofv3
+// --marker-trace) shows which call enqueued which kernels.  The marker
+// library is opened at run time; without it the ranges cost nothing.
+struct RoctxApi {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+  RoctxApi() {
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!push || !pop) push = nullptr, pop = nullptr;
+  }
+};
+
+const RoctxApi& roctx() {
+  static const RoctxApi api;
+  return api;
+}
+
+struct Range {
+  explicit Range(const char* name) {
+    if (roctx().push) roctx().push(name);
+  }
+  ~Range() {
+    if (roctx().pop) roctx().pop();
+  }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 vrn_status fail(vrn_status s, const std::string& msg) {
   g_err = msg;
@@ -357,6 +389,7 @@ void vrn_destroy(vrn_ctx* ctx) {
 }
 
 vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* out) {
+  Range range("vrn_load_field");
   vrn_status st = validate_desc(d);
   if (st != VRN_OK) return st;
   if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
@@ -539,6 +572,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
 }
 
 vrn_status vrn_unload_field(vrn_ctx* ctx, vrn_field_id field) {
+  Range range("vrn_unload_field");
   if (!ctx) return fail(VRN_ERR_INVALID_ARG, "ctx is NULL");
   std::lock_guard<std::mutex> lock(ctx->mu);
   Field* f = find_field(ctx, field);
@@ -584,6 +618,7 @@ vrn_status vrn_render_bytes(vrn_ctx* ctx, vrn_field_id field, uint32_t n_cams, u
 }
 
 vrn_status vrn_workspace_init(vrn_ctx* ctx, void* ws, uint64_t bytes, void* stream) {
+  Range range("vrn_workspace_init");
   if (!ctx || !ws) return fail(VRN_ERR_INVALID_ARG, "ctx or workspace is NULL");
   if (bytes < (uint64_t)kWsBytes) return fail(VRN_ERR_INVALID_ARG, "workspace too small");
   std::lock_guard<std::mutex> lock(ctx->mu);
@@ -600,6 +635,7 @@ static vrn_status render_common(vrn_ctx* ctx, vrn_field_id field, const vrn_came
                                 uint32_t n_cams, uint32_t W, uint32_t H, const vrn_render_opts* opts,
                                 float* d_rgba, uint32_t* d_nsamples, void* ws, uint64_t ws_bytes,
                                 void* stream) {
+  Range range(cams_dev ? "vrn_render_device_cams" : "vrn_render");
   if (!cams) return fail(VRN_ERR_INVALID_ARG, "cameras are NULL");
   vrn_status st = cams_dev ? VRN_OK : check_cams(cams, n_cams, W, H);
   if (st != VRN_OK) return st;
@@ -688,6 +724,7 @@ vrn_status vrn_read_stats(vrn_ctx* ctx, const void* ws, vrn_stats* out, void* st
 
 vrn_status vrn_rays(vrn_ctx* ctx, const vrn_camera* cams, uint32_t n_cams, uint32_t W, uint32_t H,
                     float scale, float* d_o, float* d_d, float* d_r, void* stream) {
+  Range range("vrn_rays");
   if (!ctx || !d_o || !d_d || !d_r) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
   vrn_status st = check_cams(cams, n_cams, W, H);
   if (st != VRN_OK) return st;
@@ -704,6 +741,7 @@ vrn_status vrn_rays(vrn_ctx* ctx, const vrn_camera* cams, uint32_t n_cams, uint3
 
 vrn_status vrn_march(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, uint32_t n_cams, uint32_t W,
                      uint32_t H, uint32_t* d_klist, uint32_t max_k, uint32_t* d_count, void* stream) {
+  Range range("vrn_march");
   if (!ctx || !d_count || (max_k > 0 && !d_klist)) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
   vrn_status st = check_cams(cams, n_cams, W, H);
   if (st != VRN_OK) return st;
@@ -723,6 +761,7 @@ vrn_status vrn_march(vrn_ctx* ctx, vrn_field_id field, const vrn_camera* cams, u
 
 vrn_status vrn_encode(vrn_ctx* ctx, vrn_field_id field, const float* d_xyz, const float* d_t, const float* d_r,
                       uint32_t n, float* d_feat, void* stream) {
+  Range range("vrn_encode");
   if (!ctx || !d_xyz || !d_feat) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
   std::lock_guard<std::mutex> lock(ctx->mu);
   Field* f = find_field(ctx, field);
@@ -739,6 +778,7 @@ vrn_status vrn_encode(vrn_ctx* ctx, vrn_field_id field, const float* d_xyz, cons
 
 vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const float* d_dir, uint32_t n,
                    vrn_dtype compute, float* d_sigma, float* d_rgb, void* stream) {
+  Range range("vrn_mlp");
   if (!ctx || !d_feat || !d_dir || !d_sigma || !d_rgb) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
   if (compute != VRN_F32 && compute != VRN_F16 && compute != VRN_BF16)
     return fail(VRN_ERR_INVALID_ARG, "compute must be VRN_F32, VRN_F16 or VRN_BF16");
@@ -756,6 +796,7 @@ vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const 
 
 vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_t points_per_voxel,
                           vrn_dtype compute, uint32_t* d_bits_out, float* d_max_opacity, void* stream) {
+  Range range("vrn_prune_grid");
   if (!ctx || !d_bits_out) return fail(VRN_ERR_INVALID_ARG, "ctx or d_bits_out is NULL");
   if (!finite(alpha) || alpha < 0.0f || alpha > 1.0f) return fail(VRN_ERR_INVALID_ARG, "alpha must be in [0, 1]");
   if (points_per_voxel != 4 && points_per_voxel != 1 && points_per_voxel != 8 && points_per_voxel != 27 &&
@@ -788,6 +829,7 @@ vrn_status vrn_debug_counters(vrn_ctx* ctx, uint64_t out[6], int reset) {
 }
 
 vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* stream) {
+  Range range("vrn_set_occupancy");
   if (!ctx || !d_bits) return fail(VRN_ERR_INVALID_ARG, "ctx or d_bits is NULL");
   std::lock_guard<std::mutex> lock(ctx->mu);
   Field* f = find_field(ctx, field);

@@ -13,10 +13,11 @@ constexpr int kMaxCams = VRN_MAX_CAMS;
 constexpr int kQueues = 8;          // one ray queue per XCD
 constexpr int kTile = 8;            // rays are issued in 8x8 pixel tiles
 constexpr int kBlock = 256;         // threads per render block (4 waves)
-// The FP32-MLP render kernel runs blocks of 8 waves: its 40 KiB of weights in
-// LDS are then shared by twice the waves, so LDS no longer caps it below the
-// 4 waves/SIMD its registers allow.
-constexpr int kBlockF32 = 512;
+// The FP32-MLP render kernel runs blocks of 16 waves, one block per CU: its
+// 40 KiB of weights in LDS are shared by all of them, which leaves room for
+// every ray's 16 SH values in FP32 (64 KiB) at the 4 waves/SIMD its registers
+// allow.
+constexpr int kBlockF32 = 1024;
 inline int render_block_threads(int compute) { return compute == 0 ? kBlockF32 : kBlock; }
 constexpr int kHidden = 64;
 constexpr int kCoarseWords = 1024;  // <= 32^3 bits of coarse occupancy in LDS

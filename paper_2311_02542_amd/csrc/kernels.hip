@@ -102,6 +102,21 @@ __device__ __forceinline__ void tile_encode(const FieldDev& F, const LevelDev* s
   encode_point<TAB16, PRECISE>(F, s_lv, tab, px, lstar, act, lane >> 4, feat, fetches);
 }
 
+// Per-ray SH values in FP32 for the FP32 path, laid out [lane][group g][i]
+// with c = g + 4 i: a tile's lane group reads its four values in one 16-byte
+// LDS load instead of evaluating all 16 polynomials of its sample's ray.
+__device__ __forceinline__ void store_ray_sh_f32(const FieldDev& F, const Ray& r, float4* s_sh_lane) {
+  float s[16];
+  sh_basis16(r.dx, r.dy, r.dz, s);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (uint32_t)(g + 4 * i) < F.nsh ? s[g + 4 * i] : 0.0f;
+    s_sh_lane[g] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
 // Per-ray SH values in the MFMA element type, laid out [lane][group g][c = g + 4 i].
 template <bool BF>
 __device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, uint2* s_sh_lane) {
@@ -134,7 +149,10 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
   __shared__ uint32_t s_off[kMaxCams + 1];
   __shared__ uint32_t s_rb[kMaxCams], s_re[kMaxCams];
   __shared__ uint32_t s_stats[6];
-  __shared__ uint2 s_sh[MODE == 0 ? 1 : kThreads * 4];
+  // per-ray SH values: FP32 [lane][g] float4 (FP32 path) or packed 16-bit [lane][g] uint2
+  __shared__ __align__(16) uint8_t s_sh_raw[kThreads * 4 * (MODE == 0 ? 16 : 8)];
+  uint2* s_sh = reinterpret_cast<uint2*>(s_sh_raw);
+  float4* s_sh4 = reinterpret_cast<float4*>(s_sh_raw);
   __shared__ uint32_t s_slot[kThreads];
 
   const FieldDev& F = A.F;
@@ -230,6 +248,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
           if (col < A.W && row < s_re[c]) {
             setup_ray<GEO>(F, A.cams[c], col, row, r);
             if constexpr (MODE != 0) store_ray_sh<MODE == 2>(F, r, &s_sh[threadIdx.x * 4]);
+            else store_ray_sh_f32(F, r, &s_sh4[threadIdx.x * 4]);
             pix = (c * A.H + row) * A.W + col;
             T = 1.0f;
             cr = cg = cb = 0.0f;
@@ -278,7 +297,13 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
         const int src = tile_source(&s_slot[wave_base], ns, t, lane, act);
         float feat[8], shs[4];
         tile_encode<TAB16, true>(F, s_lv, tab, src, act, lane, sx, slst, feat, st_fetch);
-        sh_select(F, shfl_f(r.dx, src), shfl_f(r.dy, src), shfl_f(r.dz, src), lane >> 4, shs);
+        {
+          const float4 v = s_sh4[(wave_base + src) * 4 + (lane >> 4)];
+          shs[0] = v.x;
+          shs[1] = v.y;
+          shs[2] = v.z;
+          shs[3] = v.w;
+        }
         float o0, lg[3];
         mlp_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, shs, lane, o0, lg);
         const int from = rank & 15;
@@ -521,6 +546,17 @@ __global__ void prune_init_kernel(FieldDev F, uint32_t* bits_out, float* max_op)
   if (w >= (n + 31u) / 32u) return;
   const uint32_t i0 = w * 32u;
   uint32_t x = i0 % G, y = (i0 / G) % G, z = i0 / (G * G);
+  if ((G & 31u) == 0u && !max_op) {
+    // the word is one row of 32 cells at fixed (y, z): 4 cells from each of
+    // 8 bricks, taken from the brick words directly
+    const uint32_t shift = 4u * (y & 3u) + 16u * (z & 3u);
+    const uint32_t b0 = (x >> 2) + F.Gb * ((y >> 2) + F.Gb * (z >> 2));
+    uint32_t out = 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < 8u; ++k) out |= (uint32_t)((F.bricks[b0 + k] >> shift) & 0xFull) << (4u * k);
+    bits_out[w] = out;
+    return;
+  }
   uint32_t out = 0u;
   for (uint32_t j = 0; j < 32u && i0 + j < n; ++j) {
     if (cell_occupied(F, x, y, z)) out |= 1u << j;

@@ -161,3 +161,35 @@ def test_prune_keeps_voxels_whose_fp16_opacity_overflows(R):
     assert kept16[sat].all()
     assert (mx16[sat] == 1.0).all()
     assert not np.isnan(mx16[np.isfinite(mx32)]).any()
+
+
+@pytest.mark.parametrize("g", [64, 33])
+def test_prune_bits_same_with_and_without_max_opacity(R, g):
+    """The output bits do not depend on whether the maximum opacities are
+    requested (rows of 32 cells are built from the brick words directly when
+    G is a multiple of 32 and no opacities are written; G = 33 takes the
+    per-cell form either way)."""
+    torch = R.torch
+    if g == 64:
+        f = synth.field_blobs64()
+    else:
+        rng = np.random.default_rng(3)
+        from gpu_common import tiny_field
+        f = tiny_field(g, rng.uniform(size=(g, g, g)) < 0.2, L=4, log2_T=12)
+    fid = R.load(f)
+    words = (g ** 3 + 31) // 32
+    a = torch.full((words,), -1, dtype=torch.int32, device="cuda")
+    b = torch.full((words,), -1, dtype=torch.int32, device="cuda")
+    mx = torch.zeros(g ** 3, dtype=torch.float32, device="cuda")
+    # alpha at the median opacity, so that about half the voxels are pruned
+    capi.vrn_prune_grid(R.ctx, fid, 0.0, b, mx, 4, "f32")
+    m = mx.cpu().numpy()
+    alpha = float(np.median(m[np.isfinite(m)]))
+    capi.vrn_prune_grid(R.ctx, fid, alpha, a, None, 4, "f32")
+    capi.vrn_prune_grid(R.ctx, fid, alpha, b, mx, 4, "f32")
+    torch.cuda.synchronize()
+    R.unload(fid)
+    assert torch.equal(a, b)
+    kept = synth.unpack_bits(a.cpu().numpy().view(np.uint32), g).ravel()
+    occ = synth.unpack_bits(np.asarray(f["occ_bits"]), g).ravel()
+    assert not (kept & ~occ).any() and 0 < kept.sum() < occ.sum()
