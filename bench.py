@@ -352,9 +352,9 @@ def precision_c3(R, crop=256, workers=16):
     """The precision workload: the 3.2 m blob field at a 2048^2 eye along its
     32-pose walk, FP16 tables with FP16 and with BF16 MLPs, against the FP32
     GPU path (whole image) and the FP64 oracle on a crop x crop window per
-    pose chosen by content (the window with the largest mean alpha: the
-    central window of many poses holds no occupied sample).  Poses whose
-    image has no content are counted and left out of the error figures."""
+    pose chosen by content (the window with the largest mean alpha).  Poses
+    whose image has no content would be counted and left out of the error
+    figures."""
     import multiprocessing
     import torch
     from paper_2311_02542_amd import synth

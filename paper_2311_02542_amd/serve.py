@@ -119,9 +119,10 @@ class _Slot:
         self.ws = torch.zeros(ws_bytes, dtype=torch.uint8, device=device)
         self.cams = torch.zeros(capi.MAX_CAMS * CAM_BYTES, dtype=torch.uint8, device=device)
         self.cams_host = torch.zeros(capi.MAX_CAMS * CAM_BYTES, dtype=torch.uint8).pin_memory()
+        self.cams_host_ptr = self.cams_host.data_ptr()
         self.rings: "collections.OrderedDict[tuple, list]" = collections.OrderedDict()
         self.busy = None          # list of requests in flight
-        self.event = None
+        self.event = torch.cuda.Event()   # recorded after each launch; reused
 
 
 class Server:
@@ -179,13 +180,15 @@ class Server:
         request completes (latency-only clients)."""
         if scene not in self.fids:
             raise ServeError(f"unknown scene {scene}")
-        if capi.vrn_check_cameras(cams, W, H) != capi.VRN_OK:
-            raise ServeError("invalid cameras: " + capi.load_library().vrn_last_error().decode())
         if len(cams) > capi.MAX_CAMS:
             raise ServeError("too many cameras in one request")
+        arr = capi.make_cameras(cams, H)
+        lib = capi.load_library()
+        if lib.vrn_check_cameras(arr, len(cams), W, H) != capi.VRN_OK:
+            raise ServeError("invalid cameras: " + lib.vrn_last_error().decode())
         if self.fixed_bytes + self.out_bytes(len(cams), W, H) > self.budget:
             raise ServeError("request can never fit the HBM budget")
-        blob = bytes(capi.make_cameras(cams, H))
+        blob = bytes(arr)
         t = time.perf_counter() if t_arrival is None else t_arrival
         deadline = None if timeout_s is None else t + float(timeout_s)
         with self.cv:
@@ -255,9 +258,13 @@ class Server:
         ns = torch.zeros((n_cams, H, W), dtype=torch.int32, device=self.device)
         graph = None
         if self.use_graphs:
+            # the graph uploads the slot's pinned cameras (a copy node, so a
+            # replay takes whatever cameras were written there) and renders
             torch.cuda.synchronize()
             graph = torch.cuda.CUDAGraph()
+            nb = n_cams * CAM_BYTES
             with torch.cuda.graph(graph, stream=slot.stream, capture_error_mode="thread_local"):
+                slot.cams[:nb].copy_(slot.cams_host[:nb], non_blocking=True)
                 capi.vrn_render_device_cams(self.ctx, self.fids[key[0]], slot.cams, n_cams, W, H, rgba, ns,
                                             self.compute, workspace=slot.ws, stream=slot.stream)
         o = _Out(rgba, ns, graph, self.out_bytes(n_cams, W, H))
@@ -325,17 +332,18 @@ class Server:
         o = self._acquire_out(slot, key, n, r0.W, r0.H)
         if o is None:
             return False
-        blob = b"".join(r.cam_blob for r in reqs)
-        ctypes.memmove(slot.cams_host.data_ptr(), blob, len(blob))
-        with torch.cuda.stream(slot.stream):
-            slot.cams[:len(blob)].copy_(slot.cams_host[:len(blob)], non_blocking=True)
+        blob = r0.cam_blob if len(reqs) == 1 else b"".join(r.cam_blob for r in reqs)
+        # the slot is idle, so the pinned buffer's previous upload has completed
+        ctypes.memmove(slot.cams_host_ptr, blob, len(blob))
+        with torch.cuda.stream(slot.stream):        # graphs replay on the current stream
             if o.graph is not None:
                 o.graph.replay()
             else:
+                slot.cams[:len(blob)].copy_(slot.cams_host[:len(blob)], non_blocking=True)
                 capi.vrn_render_device_cams(self.ctx, self.fids[r0.scene], slot.cams, n, r0.W, r0.H, o.rgba,
                                             o.ns, self.compute, workspace=slot.ws, stream=slot.stream)
-            ev = torch.cuda.Event()
-            ev.record(slot.stream)
+        ev = slot.event
+        ev.record(slot.stream)
         now = time.perf_counter()
         off = 0
         with self.lock:
@@ -481,8 +489,13 @@ def drive(server, stream, keep=False):
     t0 = time.perf_counter()
     reqs = []
     for (t, scene, cams, W, H) in stream:
-        while time.perf_counter() - t0 < t:
-            time.sleep(0)
+        while True:
+            # sleep through most of the gap (leaving the interpreter to the
+            # scheduler thread) and spin for the last fraction of a millisecond
+            left = t - (time.perf_counter() - t0)
+            if left <= 0:
+                break
+            time.sleep(left - 3e-4 if left > 6e-4 else 0)
         reqs.append(server.submit(scene, cams, W, H, t_arrival=t0 + t, keep=keep))
     server.stop(drain=True)
     wall = time.perf_counter() - t0

@@ -434,16 +434,21 @@ def cameras_room256(n: int = 1, W: int = 1024, H: int = 1024, seed_block: int = 
 
 
 def cameras_walk_3m2(n: int = 32, W: int = 2048, H: int = 2048):
-    """32 poses along a seeded walk, eye height 1.6 m +- 0.05, smooth yaw."""
+    """n poses along a seeded walk around the 3.2 m field: 3 cm steps on an
+    arc of radius 1.1 m about the cube's vertical centre line, facing the
+    centre with a smoothly varying yaw offset (a random walk of +-2 degrees
+    per step, kept within +-15), eye height 1.6 m +- 0.05."""
     rng = rng_for(3, 4)
-    yaw0 = rng.uniform(0, 2 * math.pi)
-    p = np.array([rng.uniform(1.2, 2.0), rng.uniform(1.2, 2.0)])
+    centre = np.array([1.6, 1.6])
+    radius = 1.1
+    phi = rng.uniform(0, 2 * math.pi)
+    off = 0.0
     cams = []
-    yaw = yaw0
     for i in range(n):
-        yaw += math.radians(rng.uniform(-4, 4))
-        p = p + 0.03 * np.array([math.cos(yaw), math.sin(yaw)])
-        p = np.clip(p, 0.5, 2.7)
+        phi += 0.03 / radius
+        off = float(np.clip(off + math.radians(rng.uniform(-2, 2)), -math.radians(15), math.radians(15)))
+        p = centre + radius * np.array([math.cos(phi), math.sin(phi)])
+        yaw = phi + math.pi + off                      # towards the centre, plus the offset
         z = 1.6 + rng.uniform(-0.05, 0.05)
         cams.append(camera(look_rotation(yaw, 0.0), np.array([p[0], p[1], z]), W, H, 60.0))
     return cams

@@ -35,8 +35,9 @@ def test_precision_report_blobs_3m2(R):
     """All 32 poses of the walk at the 2048^2 eye: FP16 and BF16 against the
     FP32 GPU path over every pixel; against the FP64 oracle on a 256^2 crop
     of each of the 8 poses with the most content (the crop with the largest
-    mean alpha -- the central crop of these poses is mostly empty).  Poses
-    without content are counted and excluded from the budget check."""
+    mean alpha).  Poses without content would be counted and excluded from
+    the budget check; the walk faces the field, so every pose must have
+    some."""
     torch = R.torch
     f32 = synth.field_blobs_3m2(table_dtype=np.float32)     # the field before FP16 rounding
     f16 = synth.field_blobs_3m2()                           # FP16 tables (the workload's form)
@@ -57,6 +58,7 @@ def test_precision_report_blobs_3m2(R):
     empty = sum(c < 1e-3 for c in content)
     print(f"32 poses: {empty} without content; content fraction per pose "
           + " ".join(f"{c:.3f}" for c in content))
+    assert empty == 0, "a pose of the walk sees nothing of the field"
     chosen = sorted(range(32), key=lambda i: -content[i])[:8]
     assert all(content[i] >= 1e-3 for i in chosen), "fewer than 8 poses with content"
     report = {}
