@@ -244,7 +244,8 @@ class Server:
         capi.vrn_destroy(self.ctx)
 
     def held_bytes(self):
-        """Device bytes of ring buffers currently held by finished requests."""
+        """Device bytes of ring buffers currently held by requests: in flight,
+        or finished and not yet released."""
         with self.lock:
             return sum(o.bytes for s in self.slots for ring in s.rings.values() for o in ring if o.holders)
 
