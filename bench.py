@@ -595,6 +595,10 @@ def main():
                                   "room (FP16 tables); Poisson arrivals at fixed rates",
                            "server": "FP16 MFMA, 4 slots, batching, hipGraph per bucket",
                            "baseline": "FP32, one request at a time (one-slot FIFO), no graphs, same arrival trace",
+                           "fifo_f16": "the baseline's one-slot FIFO with the FP16 path (kernel share of the gain)",
+                           "capacity_req_per_s": {m: sv[f"{m}_burst"]["req_per_s"]
+                                                  for m in ("server_f16", "baseline_f32_fifo", "fifo_f16")
+                                                  if f"{m}_burst" in sv},
                            "runs": sv}
     if cpu is not None:
         line["cpu_baseline"] = cpu
