@@ -593,7 +593,10 @@ def main():
                            "mix": "40% 256^2, 40% 1024^2, 20% 2x2048^2 stereo; scenes uniform over the "
                                   "64^2-blob field (FP32 tables), the 3.2 m blob field and the 2^20-entry "
                                   "room (FP16 tables); Poisson arrivals at fixed rates",
-                           "server": "FP16 MFMA, 4 slots, batching, hipGraph per bucket",
+                           "wait_p50_ms": head_run["wait_p50_ms"],
+                           "engine": "native scheduler thread of libvrn (vrn_server_*); results stay in a "
+                                     "device arena until released",
+                           "server": "FP16 MFMA, 4 slots, batching, hipGraph per ring buffer",
                            "baseline": "FP32, one request at a time (one-slot FIFO), no graphs, same arrival trace",
                            "fifo_f16": "the baseline's one-slot FIFO with the FP16 path (kernel share of the gain)",
                            "capacity_req_per_s": {m: sv[f"{m}_burst"]["req_per_s"]

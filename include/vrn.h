@@ -48,7 +48,9 @@ typedef enum {
   VRN_ERR_BUDGET = -4,        /* would exceed the context's HBM budget */
   VRN_ERR_DEVICE = -5,        /* no usable GPU, or a HIP runtime error */
   VRN_ERR_NOT_FOUND = -6,     /* unknown field id */
-  VRN_ERR_BUSY = -7           /* field still has renders in flight */
+  VRN_ERR_BUSY = -7,          /* field still in use; request not finished */
+  VRN_ERR_TIMEOUT = -8,       /* serving: the request passed its deadline */
+  VRN_ERR_CANCELLED = -9      /* serving: the request was cancelled */
 } vrn_status;
 
 typedef enum { VRN_F32 = 0, VRN_F16 = 1, VRN_BF16 = 2 } vrn_dtype;
@@ -155,9 +157,11 @@ const char* vrn_last_error(void);
  * FP32, FP16 and BF16).  The field stays resident until unloaded. */
 vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* desc, vrn_field_id* out);
 
-/* Free a field.  VRN_ERR_BUSY while renders that use it are still running.
- * Renders enqueued under HIP graph capture are not tracked: the caller keeps
- * the field loaded while a graph that renders it can still be replayed. */
+/* Free a field.  VRN_ERR_BUSY while renders that use it are still running,
+ * or while a serving engine holds output buffers (and their graphs) for it
+ * (vrn_server_evict, vrn_server_destroy).  Renders enqueued under the
+ * caller's own HIP graph capture are not tracked: the caller keeps the field
+ * loaded while a graph that renders it can still be replayed. */
 vrn_status vrn_unload_field(vrn_ctx* ctx, vrn_field_id field);
 
 /* Device bytes held by a resident field. */
@@ -285,6 +289,139 @@ vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_
  * hip_stream.  Renders of this field on other streams must be ordered by
  * the caller. */
 vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* hip_stream);
+
+/* ---- serving engine: continuous batching of render requests ----
+ *
+ * A serving loop around the single-kernel renderer of Sec. 5, whose
+ * latency percentiles matter because the p99 frame rate is the quality
+ * measure of the performance evaluation (Sec. 6): requests of mixed
+ * resolutions over the resident fields of one context are queued and
+ * launched as slots free up, and a finished request's result stays in
+ * device memory until the client releases it.
+ *
+ *   - A slot is a HIP stream of default priority with its own workspace
+ *     and camera buffers; up to n_slots renders run at once.
+ *   - When a slot is free, the oldest pending request is launched together
+ *     with the single-camera requests of the same field and size queued
+ *     behind it, up to max_batch cameras in one launch.
+ *   - A bucket is (field, W, H, cameras in the launch).  Each slot keeps,
+ *     per bucket, a ring of output buffers carved from one device arena;
+ *     with use_graphs each buffer has a captured HIP graph (camera upload
+ *     from the slot's pinned buffer, then the render into that buffer), so
+ *     a launch is a host memcpy and one graph launch.
+ *   - Admission is the arena: every ring buffer, held by a client or free,
+ *     lives in it; free buffers are evicted least-recently-used when a new
+ *     one does not fit, and a request that fits only once held results are
+ *     released waits for them.  A request larger than the arena is refused
+ *     at submission.
+ *   - A request may carry a deadline: still queued at its deadline it is
+ *     never launched; finished after it, its result is discarded.
+ *   - One scheduler thread per engine makes every device call of serving;
+ *     the vrn_server_* calls below are thread-safe.  Times are seconds on
+ *     vrn_server_clock() (a monotonic clock).
+ */
+typedef struct vrn_server vrn_server;
+
+typedef struct {
+  uint32_t n_slots;           /* concurrent renders, 1..16 */
+  uint32_t max_batch;         /* cameras per launch when requests merge, 1..VRN_MAX_CAMS */
+  int32_t use_graphs;         /* 1: one captured HIP graph per ring buffer; 0: eager launches */
+  vrn_render_opts render;     /* every render of the engine (compute, output, ...) */
+  void* d_arena;              /* device memory for results, owned by the caller and
+                                 untouched by the engine outside its ring buffers;
+                                 NULL: the engine allocates arena_bytes itself */
+  uint64_t arena_bytes;       /* >= 256 */
+} vrn_server_opts;
+
+#define VRN_SERVE_RELEASE_ON_DONE 1u  /* latency-only client: the buffer returns to its ring
+                                         at completion (the record stays until release) */
+
+typedef struct {
+  double t_arrival;           /* arrival on vrn_server_clock(); <= 0: the time of the call */
+  double timeout_s;           /* arrival-to-completion bound; 0: none */
+  uint32_t flags;             /* VRN_SERVE_* */
+} vrn_request_opts;
+
+typedef struct {
+  int32_t status;             /* VRN_OK, VRN_ERR_TIMEOUT, VRN_ERR_CANCELLED, VRN_ERR_BUDGET
+                                 (could never be admitted), VRN_ERR_NOT_FOUND (field
+                                 unloaded), VRN_ERR_DEVICE; VRN_ERR_BUSY: not finished */
+  vrn_field_id field;
+  uint32_t n_cams, W, H;
+  float* d_rgba;              /* device [n_cams][H][W][4] in the arena, valid until
+                                 vrn_server_release; NULL unless status is VRN_OK and
+                                 the result is held */
+  uint32_t* d_nsamples;       /* device [n_cams][H][W] evaluated samples, as d_rgba */
+  double t_arrival, t_launch, t_done;  /* t_launch = 0: never launched */
+} vrn_served;
+
+typedef struct {
+  uint64_t arena_bytes, used_bytes, held_bytes, largest_free_bytes;
+  uint64_t pending, running, requests;  /* queued; in flight; submitted and not released */
+  uint64_t buffers, buckets;  /* ring buffers; distinct (slot, bucket) rings */
+  uint64_t launches, graph_launches, merged_requests, captures, evictions;
+  uint64_t completed, failed;
+} vrn_serve_stats;
+
+/* Create an engine over ctx's resident fields.  The engine starts held (no
+ * launches) until vrn_server_hold(sv, 0).  VRN_ERR_INVALID_ARG for options
+ * out of range, VRN_ERR_OUT_OF_MEMORY / VRN_ERR_DEVICE when its streams,
+ * workspaces or arena cannot be made.  ctx must outlive the engine. */
+vrn_status vrn_server_create(vrn_ctx* ctx, const vrn_server_opts* opts, vrn_server** out);
+
+/* Stop the scheduler, wait for renders in flight, free every buffer and
+ * graph, and unpin the fields.  Results not yet released become invalid.
+ * NULL is a no-op. */
+void vrn_server_destroy(vrn_server* sv);
+
+/* hold != 0: launch nothing new (completions, deadlines and cancellations
+ * are still processed); hold = 0: serve. */
+vrn_status vrn_server_hold(vrn_server* sv, int hold);
+
+/* Allocate (and with use_graphs capture) one ring buffer per slot for the
+ * bucket (field, W, H, n_cams) if the slot has none, so that serving does
+ * not capture.  Waits for the slot's render in flight, if any.
+ * VRN_ERR_BUDGET when the buffer does not fit the arena's free space. */
+vrn_status vrn_server_prepare(vrn_server* sv, vrn_field_id field, uint32_t n_cams, uint32_t W, uint32_t H);
+
+/* Queue a request of n_cams host cameras (validated as in vrn_render,
+ * copied) of W x H pixels of `field`; opts may be NULL.  *id names it in
+ * the calls below.  VRN_ERR_BUDGET if its outputs exceed the arena,
+ * VRN_ERR_NOT_FOUND for an unknown field. */
+vrn_status vrn_server_submit(vrn_server* sv, vrn_field_id field, const vrn_camera* cams, uint32_t n_cams,
+                             uint32_t W, uint32_t H, const vrn_request_opts* opts, uint64_t* id);
+
+/* Wait up to max_wait_s (0: do not wait) for request id, then describe it
+ * in *out.  VRN_OK once the request has finished (its outcome is
+ * out->status); VRN_ERR_BUSY if it has not; VRN_ERR_NOT_FOUND for an
+ * unknown or released id. */
+vrn_status vrn_server_wait(vrn_server* sv, uint64_t id, double max_wait_s, vrn_served* out);
+
+/* Forget a finished request and return its output buffer to its ring; its
+ * d_rgba / d_nsamples must no longer be read.  VRN_ERR_BUSY while it has
+ * not finished (cancel it first). */
+vrn_status vrn_server_release(vrn_server* sv, uint64_t id);
+
+/* Cancel a request: a queued one finishes at once with VRN_ERR_CANCELLED;
+ * a running one does so when its render completes (the result is
+ * discarded).  VRN_ERR_BUSY when it has already finished. */
+vrn_status vrn_server_cancel(vrn_server* sv, uint64_t id);
+
+/* Wait up to max_wait_s until nothing is queued or running.  VRN_ERR_BUSY
+ * if that does not happen in time. */
+vrn_status vrn_server_drain(vrn_server* sv, double max_wait_s);
+
+/* Free the free ring buffers (and graphs) of `field`, or of every field
+ * when field is 0, and unpin fields left without buffers.  VRN_ERR_BUSY if
+ * buffers of it remain because they are held or in flight. */
+vrn_status vrn_server_evict(vrn_server* sv, vrn_field_id field);
+
+/* Counters and memory of the engine; VRN_ERR_DEVICE (with the counters
+ * filled) once a HIP error has been seen in serving. */
+vrn_status vrn_server_stats(vrn_server* sv, vrn_serve_stats* out);
+
+/* The engine's clock: seconds, monotonic. */
+double vrn_server_clock(void);
 
 /* ---- debugging ---- */
 

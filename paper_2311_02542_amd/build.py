@@ -7,13 +7,13 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libvrn.so")
-SOURCES = [os.path.join(PKG, "csrc", "kernels.hip"), os.path.join(PKG, "csrc", "capi.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("kernels.hip", "capi.cpp", "server.cpp")]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # canonical FP32 geometry: no contraction, IEEE divide and sqrt
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result", "-Wno-unused-value",
+    "-Wno-unused-result", "-Wno-unused-value", "-pthread",
 ]
 
 

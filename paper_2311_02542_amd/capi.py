@@ -19,11 +19,12 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 VRN_OK, VRN_ERR_INVALID_ARG, VRN_ERR_UNSUPPORTED, VRN_ERR_OUT_OF_MEMORY = 0, -1, -2, -3
 VRN_ERR_BUDGET, VRN_ERR_DEVICE, VRN_ERR_NOT_FOUND, VRN_ERR_BUSY = -4, -5, -6, -7
+VRN_ERR_TIMEOUT, VRN_ERR_CANCELLED = -8, -9
 VRN_F32, VRN_F16, VRN_BF16 = 0, 1, 2
 DTYPES = {"f32": VRN_F32, "f16": VRN_F16, "bf16": VRN_BF16}
 STATUS_NAMES = {0: "VRN_OK", -1: "VRN_ERR_INVALID_ARG", -2: "VRN_ERR_UNSUPPORTED",
                 -3: "VRN_ERR_OUT_OF_MEMORY", -4: "VRN_ERR_BUDGET", -5: "VRN_ERR_DEVICE",
-                -6: "VRN_ERR_NOT_FOUND", -7: "VRN_ERR_BUSY"}
+                -6: "VRN_ERR_NOT_FOUND", -7: "VRN_ERR_BUSY", -8: "VRN_ERR_TIMEOUT", -9: "VRN_ERR_CANCELLED"}
 MAX_CAMS = 16
 
 c_f = ctypes.c_float
@@ -61,6 +62,31 @@ OUTPUTS = {"pq": VRN_OUT_PQ, "linear": VRN_OUT_LINEAR, "srgb": VRN_OUT_SRGB}
 class VrnStats(ctypes.Structure):
     _fields_ = [("rays", c_u64), ("samples", c_u64), ("level_fetches", c_u64),
                 ("march_steps", c_u64), ("rounds", c_u64), ("tiles", c_u64)]
+
+
+class VrnServerOpts(ctypes.Structure):
+    _fields_ = [("n_slots", c_u32), ("max_batch", c_u32), ("use_graphs", c_i32), ("render", VrnRenderOpts),
+                ("d_arena", c_vp), ("arena_bytes", c_u64)]
+
+
+VRN_SERVE_RELEASE_ON_DONE = 1
+
+
+class VrnRequestOpts(ctypes.Structure):
+    _fields_ = [("t_arrival", ctypes.c_double), ("timeout_s", ctypes.c_double), ("flags", c_u32)]
+
+
+class VrnServed(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("field", c_u32), ("n_cams", c_u32), ("W", c_u32), ("H", c_u32),
+                ("d_rgba", c_vp), ("d_nsamples", c_vp), ("t_arrival", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class VrnServeStats(ctypes.Structure):
+    _fields_ = [(name, c_u64) for name in (
+        "arena_bytes", "used_bytes", "held_bytes", "largest_free_bytes", "pending", "running", "requests",
+        "buffers", "buckets", "launches", "graph_launches", "merged_requests", "captures", "evictions",
+        "completed", "failed")]
 
 
 class VrnError(RuntimeError):
@@ -108,6 +134,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vrn_prune_grid": (c_i32, [c_vp, c_u32, c_f, c_u32, c_i32, c_vp, c_vp, c_vp]),
         "vrn_set_occupancy": (c_i32, [c_vp, c_u32, c_vp, c_vp]),
         "vrn_debug_counters": (c_i32, [c_vp, P(c_u64), ctypes.c_int]),
+        "vrn_server_create": (c_i32, [c_vp, P(VrnServerOpts), P(c_vp)]),
+        "vrn_server_destroy": (None, [c_vp]),
+        "vrn_server_hold": (c_i32, [c_vp, ctypes.c_int]),
+        "vrn_server_prepare": (c_i32, [c_vp, c_u32, c_u32, c_u32, c_u32]),
+        "vrn_server_submit": (c_i32, [c_vp, c_u32, P(VrnCamera), c_u32, c_u32, c_u32, P(VrnRequestOpts),
+                                      P(c_u64)]),
+        "vrn_server_wait": (c_i32, [c_vp, c_u64, ctypes.c_double, P(VrnServed)]),
+        "vrn_server_release": (c_i32, [c_vp, c_u64]),
+        "vrn_server_cancel": (c_i32, [c_vp, c_u64]),
+        "vrn_server_drain": (c_i32, [c_vp, ctypes.c_double]),
+        "vrn_server_evict": (c_i32, [c_vp, c_u32]),
+        "vrn_server_stats": (c_i32, [c_vp, P(VrnServeStats)]),
+        "vrn_server_clock": (ctypes.c_double, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -377,6 +416,99 @@ def vrn_debug_counters(ctx, reset=False) -> dict:
 def vrn_set_occupancy(ctx, fid, bits, stream=None):
     lib = load_library()
     _check(lib.vrn_set_occupancy(ctx, fid, _ptr(bits), _stream(stream)), lib)
+
+
+# ---------------------------------------------------------------------------
+# serving engine
+# ---------------------------------------------------------------------------
+
+def vrn_server_create(ctx, arena_bytes, d_arena=None, n_slots=4, max_batch=4, use_graphs=True, compute="f16",
+                      output=None, exposure_ev=0.0):
+    """Create a serving engine (held: call vrn_server_hold(sv, False) to
+    serve).  d_arena: a device tensor or address of >= arena_bytes, or None
+    for an arena the engine allocates."""
+    lib = load_library()
+    o = VrnServerOpts()
+    o.n_slots, o.max_batch, o.use_graphs = int(n_slots), int(max_batch), int(bool(use_graphs))
+    o.render = render_opts(compute, output=output, exposure_ev=exposure_ev)
+    o.d_arena = None if d_arena is None else _ptr(d_arena).value
+    o.arena_bytes = int(arena_bytes)
+    sv = c_vp()
+    _check(lib.vrn_server_create(ctx, ctypes.byref(o), ctypes.byref(sv)), lib)
+    return sv
+
+
+def vrn_server_destroy(sv):
+    load_library().vrn_server_destroy(sv)
+
+
+def vrn_server_hold(sv, hold: bool):
+    lib = load_library()
+    _check(lib.vrn_server_hold(sv, int(bool(hold))), lib)
+
+
+def vrn_server_prepare(sv, fid, n_cams, W, H):
+    lib = load_library()
+    _check(lib.vrn_server_prepare(sv, fid, n_cams, W, H), lib)
+
+
+def vrn_server_submit(sv, fid, cams, W, H, t_arrival=0.0, timeout_s=0.0, flags=0, cam_array=None) -> int:
+    """Queue a request; returns its id.  cam_array: the cameras already
+    marshalled by make_cameras (skips the conversion)."""
+    lib = load_library()
+    arr = make_cameras(cams, H) if cam_array is None else cam_array
+    ro = VrnRequestOpts(float(t_arrival), float(timeout_s), int(flags))
+    rid = c_u64()
+    _check(lib.vrn_server_submit(sv, fid, arr, len(arr), W, H, ctypes.byref(ro), ctypes.byref(rid)), lib)
+    return int(rid.value)
+
+
+def vrn_server_wait(sv, rid, max_wait_s=0.0):
+    """(finished, VrnServed) for request rid after waiting up to max_wait_s."""
+    lib = load_library()
+    out = VrnServed()
+    st = lib.vrn_server_wait(sv, rid, float(max_wait_s), ctypes.byref(out))
+    if st == VRN_ERR_BUSY:
+        return False, out
+    _check(st, lib)
+    return True, out
+
+
+def vrn_server_release(sv, rid):
+    lib = load_library()
+    _check(lib.vrn_server_release(sv, rid), lib)
+
+
+def vrn_server_cancel(sv, rid) -> bool:
+    """True if the request was pending or running (it will finish cancelled);
+    False if it had already finished."""
+    lib = load_library()
+    st = lib.vrn_server_cancel(sv, rid)
+    if st == VRN_ERR_BUSY:
+        return False
+    _check(st, lib)
+    return True
+
+
+def vrn_server_drain(sv, max_wait_s=60.0):
+    lib = load_library()
+    _check(lib.vrn_server_drain(sv, float(max_wait_s)), lib)
+
+
+def vrn_server_evict(sv, fid=0):
+    lib = load_library()
+    _check(lib.vrn_server_evict(sv, fid), lib)
+
+
+def vrn_server_stats(sv) -> dict:
+    lib = load_library()
+    st = VrnServeStats()
+    _check(lib.vrn_server_stats(sv, ctypes.byref(st)), lib)
+    return {name: int(getattr(st, name)) for name, _ in VrnServeStats._fields_}
+
+
+def vrn_server_clock() -> float:
+    return float(load_library().vrn_server_clock())
 
 
 # ---------------------------------------------------------------------------

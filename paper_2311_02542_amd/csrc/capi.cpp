@@ -69,6 +69,8 @@ struct Field {
   // at load time and re-recorded by every such render (those renders share
   // one scratch array, so the caller serialises them on the device)
   hipEvent_t noalloc_ev = nullptr;
+  // output buffers of serving engines whose graphs render this field
+  int pins = 0;
 };
 
 
@@ -341,6 +343,22 @@ vrn_status do_render(vrn_ctx* ctx, Field* f, const vrn_camera* d_cams, uint32_t 
 
 }  // namespace
 
+namespace vrn {
+
+vrn_status set_error(vrn_status s, const char* msg) { return fail(s, msg); }
+
+int ctx_device(const vrn_ctx* ctx) { return ctx->device; }
+
+vrn_status field_pin(vrn_ctx* ctx, vrn_field_id field, int delta) {
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Field* f = find_field(ctx, field);
+  if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
+  f->pins += delta;
+  return VRN_OK;
+}
+
+}  // namespace vrn
+
 extern "C" {
 
 const char* vrn_last_error(void) { return g_err.c_str(); }
@@ -581,6 +599,7 @@ vrn_status vrn_unload_field(vrn_ctx* ctx, vrn_field_id field) {
   for (hipEvent_t ev : f->events)
     if (hipEventQuery(ev) == hipErrorNotReady) return fail(VRN_ERR_BUSY, "field has renders in flight");
   if (hipEventQuery(f->noalloc_ev) == hipErrorNotReady) return fail(VRN_ERR_BUSY, "field has renders in flight");
+  if (f->pins > 0) return fail(VRN_ERR_BUSY, "a serving engine holds output buffers of this field");
   ctx->used -= f->bytes;
   ctx->fields.erase(field);
   free_field(f);

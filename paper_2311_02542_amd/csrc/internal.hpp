@@ -143,4 +143,12 @@ hipError_t launch_set_occupancy(const FieldDev& F, const uint32_t* bits, hipStre
 hipError_t launch_mlp(const FieldDev& F, const float* feat, const float* dir, uint32_t n,
                       int compute, float* sigma, float* rgb, hipStream_t s);
 
+// Shared by the C ABI (capi.cpp) with the serving engine (server.cpp).
+// set_error records vrn_last_error() for this thread and returns s.
+vrn_status set_error(vrn_status s, const char* msg);
+int ctx_device(const vrn_ctx* ctx);
+// Pin (delta = +1) or unpin (-1) a resident field: vrn_unload_field refuses
+// a pinned field, whose device pointers live on in captured graphs.
+vrn_status field_pin(vrn_ctx* ctx, vrn_field_id field, int delta);
+
 }  // namespace vrn

@@ -1,7 +1,9 @@
 /*
  * A plain C11 client of the renderer's C ABI (include/vrn.h), with no Python
  * and no C++: it builds a tiny field in C, renders it through vrn_render and
- * checks the result against the compositing closed form (Sec. 4.1, Eq. 2).
+ * checks the result against the compositing closed form (Sec. 4.1, Eq. 2),
+ * then serves the same camera through the serving engine (vrn_server_*) and
+ * checks that every served result has the direct render's bits.
  *
  * The field has all-zero hash tables, MLP weights and biases, so every
  * evaluated sample has density exp(0) = 1 and color sigmoid(0) = 1/2.  With
@@ -129,10 +131,58 @@ int main(void) {
   s = vrn_render(ctx, fid, &cam, 0, W, H, &opts, d_rgba, d_n, NULL, 0, NULL);
   const int err_ok = s == VRN_ERR_INVALID_ARG && strlen(vrn_last_error()) > 0;
 
+  /* the serving engine: the same camera served (graphs, merged launches,
+   * an engine-owned arena) gives the direct render's bits */
+  vrn_server_opts so;
+  memset(&so, 0, sizeof(so));
+  so.n_slots = 2;
+  so.max_batch = 4;
+  so.use_graphs = 1;
+  so.render = opts;
+  so.arena_bytes = 1u << 20;
+  vrn_server* sv = NULL;
+  if ((s = vrn_server_create(ctx, &so, &sv)) != VRN_OK) return fail_call("vrn_server_create", s);
+  if ((s = vrn_server_prepare(sv, fid, 1, W, H)) != VRN_OK) return fail_call("vrn_server_prepare", s);
+  enum { NREQ = 6 };
+  uint64_t ids[NREQ];
+  for (int i = 0; i < NREQ; ++i) {
+    vrn_request_opts ro;
+    memset(&ro, 0, sizeof(ro));
+    ro.flags = (i == NREQ - 1) ? VRN_SERVE_RELEASE_ON_DONE : 0u;
+    if ((s = vrn_server_submit(sv, fid, &cam, 1, W, H, &ro, &ids[i])) != VRN_OK)
+      return fail_call("vrn_server_submit", s);
+  }
+  if ((s = vrn_server_hold(sv, 0)) != VRN_OK) return fail_call("vrn_server_hold", s);
+  if ((s = vrn_server_drain(sv, 60.0)) != VRN_OK) return fail_call("vrn_server_drain", s);
+  int served_bad = 0;
+  float srgba[4 * W * H];
+  for (int i = 0; i < NREQ; ++i) {
+    vrn_served out;
+    if ((s = vrn_server_wait(sv, ids[i], 10.0, &out)) != VRN_OK) return fail_call("vrn_server_wait", s);
+    if (out.status != VRN_OK || !(out.t_done >= out.t_launch && out.t_launch >= out.t_arrival)) ++served_bad;
+    if (i == NREQ - 1) {
+      served_bad += out.d_rgba != NULL; /* returned to its ring at completion */
+    } else if (out.d_rgba == NULL ||
+               hipMemcpy(srgba, out.d_rgba, sizeof(srgba), hipMemcpyDeviceToHost) != hipSuccess ||
+               memcmp(srgba, rgba, sizeof(srgba)) != 0) {
+      ++served_bad;
+    }
+  }
+  /* the engine's buffers pin the field */
+  const int pinned_ok = vrn_unload_field(ctx, fid) == VRN_ERR_BUSY;
+  for (int i = 0; i < NREQ; ++i)
+    if ((s = vrn_server_release(sv, ids[i])) != VRN_OK) return fail_call("vrn_server_release", s);
+  vrn_serve_stats st;
+  if ((s = vrn_server_stats(sv, &st)) != VRN_OK) return fail_call("vrn_server_stats", s);
+  if (st.completed != NREQ || st.held_bytes != 0 || st.requests != 0) ++served_bad;
+  if ((s = vrn_server_evict(sv, 0)) != VRN_OK) return fail_call("vrn_server_evict", s);
+  vrn_server_destroy(sv);
+
   hipFree(d_rgba);
   hipFree(d_n);
   if ((s = vrn_unload_field(ctx, fid)) != VRN_OK) return fail_call("vrn_unload_field", s);
   vrn_destroy(ctx);
-  printf("pixels with samples %d of %d, mismatches %d, error path %s\n", hit, W * H, bad, err_ok ? "ok" : "wrong");
-  return (bad == 0 && hit == W * H && err_ok) ? 0 : 1;
+  printf("pixels with samples %d of %d, mismatches %d, error path %s, served mismatches %d, pin %s\n", hit,
+         W * H, bad, err_ok ? "ok" : "wrong", served_bad, pinned_ok ? "ok" : "wrong");
+  return (bad == 0 && hit == W * H && err_ok && served_bad == 0 && pinned_ok) ? 0 : 1;
 }

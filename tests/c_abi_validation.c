@@ -164,6 +164,32 @@ int main(void) {
   expect("set occupancy", vrn_set_occupancy(NULL, 1, NULL, NULL), VRN_ERR_INVALID_ARG);
   vrn_destroy(NULL);
 
+  /* serving engine: NULL handles and options out of range */
+  vrn_server* sv = NULL;
+  vrn_server_opts so;
+  memset(&so, 0, sizeof(so));
+  so.n_slots = 2;
+  so.max_batch = 4;
+  so.arena_bytes = 1u << 20;
+  expect("server, NULL context", vrn_server_create(NULL, &so, &sv), VRN_ERR_INVALID_ARG);
+  uint64_t rid = 0;
+  vrn_served served;
+  vrn_serve_stats sst;
+  expect("submit, NULL server", vrn_server_submit(NULL, 1, cams, 1, 100, 100, NULL, &rid), VRN_ERR_INVALID_ARG);
+  expect("wait, NULL server", vrn_server_wait(NULL, 1, 0.0, &served), VRN_ERR_INVALID_ARG);
+  expect("hold, NULL server", vrn_server_hold(NULL, 1), VRN_ERR_INVALID_ARG);
+  expect("prepare, NULL server", vrn_server_prepare(NULL, 1, 1, 100, 100), VRN_ERR_INVALID_ARG);
+  expect("release, NULL server", vrn_server_release(NULL, 1), VRN_ERR_INVALID_ARG);
+  expect("cancel, NULL server", vrn_server_cancel(NULL, 1), VRN_ERR_INVALID_ARG);
+  expect("drain, NULL server", vrn_server_drain(NULL, 0.0), VRN_ERR_INVALID_ARG);
+  expect("evict, NULL server", vrn_server_evict(NULL, 0), VRN_ERR_INVALID_ARG);
+  expect("server stats, NULL server", vrn_server_stats(NULL, &sst), VRN_ERR_INVALID_ARG);
+  vrn_server_destroy(NULL);
+  if (!(vrn_server_clock() > 0.0)) {
+    printf("MISMATCH server clock\n");
+    ++failures;
+  }
+
   printf("%d mismatches\n", failures);
   return failures == 0 ? 0 : 1;
 }

@@ -171,3 +171,60 @@ def test_field_file_round_trip_two_readers(tmp_path):
     for name, t in capi.VrnFieldDesc._fields_:
         if t in (capi.c_u32, capi.c_i32, capi.c_f):
             assert getattr(d1, name) == getattr(d2, name), name
+
+
+def test_server_entry_points_validate_on_host(lib):
+    """The serving engine's entry points refuse NULL handles and options out
+    of range before touching a context or the device."""
+    P = ctypes.byref
+    out = ctypes.c_void_p()
+    opts = capi.VrnServerOpts()
+    opts.n_slots, opts.max_batch, opts.use_graphs, opts.arena_bytes = 2, 4, 1, 1 << 20
+    opts.render = capi.render_opts("f16")
+    assert lib.vrn_server_create(None, P(opts), P(out)) == capi.VRN_ERR_INVALID_ARG
+    # a stand-in context handle: every case below is refused before it is read
+    dummy = ctypes.create_string_buffer(64)
+    ctx = ctypes.c_void_p(ctypes.addressof(dummy))
+    assert lib.vrn_server_create(ctx, None, P(out)) == capi.VRN_ERR_INVALID_ARG
+    bad = [("n_slots", 0), ("n_slots", 17), ("max_batch", 0), ("max_batch", capi.MAX_CAMS + 1),
+           ("use_graphs", 2), ("arena_bytes", 255)]
+    for name, v in bad:
+        o = capi.VrnServerOpts.from_buffer_copy(opts)
+        setattr(o, name, v)
+        assert lib.vrn_server_create(ctx, P(o), P(out)) == capi.VRN_ERR_INVALID_ARG, name
+        assert out.value is None
+    o = capi.VrnServerOpts.from_buffer_copy(opts)
+    o.render.compute = 7
+    assert lib.vrn_server_create(ctx, P(o), P(out)) == capi.VRN_ERR_INVALID_ARG
+    o = capi.VrnServerOpts.from_buffer_copy(opts)
+    o.render.exposure_ev = math.inf
+    assert lib.vrn_server_create(ctx, P(o), P(out)) == capi.VRN_ERR_INVALID_ARG
+    o = capi.VrnServerOpts.from_buffer_copy(opts)
+    o.d_arena = 0x1000 + 16                     # not 256-byte aligned
+    assert lib.vrn_server_create(ctx, P(o), P(out)) == capi.VRN_ERR_INVALID_ARG
+    assert "aligned" in lib.vrn_last_error().decode()
+    # NULL engine handle
+    rid = ctypes.c_uint64()
+    served = capi.VrnServed()
+    st = capi.VrnServeStats()
+    arr = capi.make_cameras([_cam()], 64)
+    assert lib.vrn_server_submit(None, 1, arr, 1, 64, 64, None, P(rid)) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_wait(None, 1, 0.0, P(served)) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_hold(None, 1) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_prepare(None, 1, 1, 64, 64) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_release(None, 1) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_cancel(None, 1) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_drain(None, 0.0) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_evict(None, 0) == capi.VRN_ERR_INVALID_ARG
+    assert lib.vrn_server_stats(None, P(st)) == capi.VRN_ERR_INVALID_ARG
+    lib.vrn_server_destroy(None)                # a no-op
+
+
+def test_server_clock_is_monotonic_seconds(lib):
+    import time
+    a = capi.vrn_server_clock()
+    m = time.monotonic()
+    time.sleep(0.01)
+    b = capi.vrn_server_clock()
+    assert 0.009 < b - a < 1.0
+    assert abs(a - m) < 1.0                     # CLOCK_MONOTONIC, as time.monotonic

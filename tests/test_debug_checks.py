@@ -18,6 +18,7 @@ from paper_2311_02542_amd import capi
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2311_02542_amd", "csrc")
+from paper_2311_02542_amd.build import SOURCES  # noqa: E402
 HIPCC = "/opt/rocm/bin/hipcc"
 
 
@@ -48,7 +49,7 @@ def test_debug_build_counts_no_violations(tmp_path):
              "-fhip-fp32-correctly-rounded-divide-sqrt -Xclang -target-feature -Xclang -packed-fp32-ops "
              "-Wno-unused-result -Wno-unused-value -DVRN_DEBUG_CHECKS").split()
     res = subprocess.run([HIPCC, *flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                          os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "capi.cpp"), "-o", lib],
+                          *SOURCES, "-o", lib],
                          capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-3000:]
     res = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "debug_checks_driver.py"), lib],

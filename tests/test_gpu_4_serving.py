@@ -1,10 +1,11 @@
-"""Serving systems tests: HIP graph replay equals eager launches (several
-replays with eager work and synchronisation in between), a request gives the
-same result alone and inside a concurrent mix (bitwise: every ray's
-arithmetic is independent of batch composition), served results of all
-three resident scenes held to the FP64 oracle, HBM-budget admission and
-queueing (held results count against the budget), timeouts and
-cancellation, and unload of a busy field."""
+"""Serving systems tests over the native serving engine: HIP graph replay
+equals eager launches (several replays with eager work and synchronisation
+in between), a request gives the same result alone and inside a concurrent
+mix (bitwise: every ray's arithmetic is independent of batch composition),
+served results of all three resident scenes held to the FP64 oracle,
+HBM-budget admission and queueing (held results count against the budget),
+hold and drain, timeouts and cancellation, fields pinned by the engine's
+buffers, and unload of a busy field."""
 import threading
 import time
 
@@ -127,24 +128,57 @@ def test_admission_budget_and_queueing():
     capi.vrn_destroy(ctx)
 
 
-def test_drain_waits_for_a_batch_being_launched():
-    """stop(drain=True) must not return while the loop holds a batch it has
-    taken from the queue but not yet put on a slot: _launch is slowed down
-    here so that a drain check always falls into that window."""
+def test_hold_then_drain():
+    """Requests submitted while the engine is held are queued, not launched;
+    once serving, stop(drain=True) returns only when every one of them has
+    finished."""
     need_gpu()
     srv = serve.Server({"A": synth.field_blobs64()}, 8 << 30, n_slots=1, compute="f16", use_graphs=False)
-    launch = srv._launch
-
-    def slow_launch(slot, reqs):
-        time.sleep(0.05)
-        return launch(slot, reqs)
-
-    srv._launch = slow_launch
-    srv.start()
-    reqs = [srv.submit("A", *synth.request_cameras("A", "preview", 7 + i)) for i in range(3)]
-    srv.stop(drain=True)
     try:
+        reqs = [srv.submit("A", *synth.request_cameras("A", "preview", 7 + i)) for i in range(6)]
+        time.sleep(0.02)
+        st = srv.stats()
+        assert st["pending"] == 6 and st["launches"] == 0
+        assert not any(r.done.is_set() for r in reqs)
+        srv.start()
+        srv.stop(drain=True)
+        st = srv.stats()
+        assert st["pending"] == 0 and st["running"] == 0
         assert all(r.done.is_set() and r.error is None for r in reqs)
+        assert st["completed"] == 6 and st["launches"] + st["merged_requests"] == 6
+    finally:
+        srv.close()
+
+
+def test_engine_pins_fields_of_its_buffers():
+    """A field whose ring buffers (and graphs) the engine holds cannot be
+    unloaded until they are evicted; a request for an unloaded field is
+    refused."""
+    need_gpu()
+    srv = serve.Server(_fields(), 4 << 30, n_slots=2, compute="f16", use_graphs=True)
+    try:
+        srv.warmup([(256, 256, 1)])
+        fid = srv.fids["B"]
+        with pytest.raises(capi.VrnError) as ei:
+            capi.vrn_unload_field(srv.ctx, fid)
+        assert ei.value.status == capi.VRN_ERR_BUSY
+        before = srv.stats()
+        capi.vrn_server_evict(srv.sv, fid)
+        after = srv.stats()
+        assert after["buffers"] == before["buffers"] - 2 and after["used_bytes"] < before["used_bytes"]
+        capi.vrn_unload_field(srv.ctx, fid)
+        del srv.fids["B"]
+        with pytest.raises(serve.ServeError):
+            srv.submit("B", *synth.request_cameras("B", "preview", 1))
+        srv.fids["B"] = fid                  # submit by id after the unload
+        with pytest.raises(serve.ServeError):
+            srv.submit("B", *synth.request_cameras("B", "preview", 1))
+        del srv.fids["B"]
+        # the other fields still serve
+        srv.start()
+        r = srv.submit("C", *synth.request_cameras("C", "preview", 2))
+        srv.stop(drain=True)
+        assert r.error is None and r.result is not None
     finally:
         srv.close()
 
@@ -178,12 +212,15 @@ def test_warmup_captures_buckets_and_serves_exactly():
     srv = serve.Server(_fields(), 4 << 30, n_slots=2, compute="f16", use_graphs=True)
     shapes = [(256, 256, 1), (256, 256, 2)]
     srv.warmup(shapes)
-    keys = {k for s in srv.slots for k in s.rings}
-    assert keys == {(sc, w, h, n, "f16") for sc in ("A", "B", "C") for (w, h, n) in shapes}
+    st0 = srv.stats()
+    # one ring buffer, with its graph, per slot, scene and shape
+    assert st0["buffers"] == st0["buckets"] == st0["captures"] == 2 * 3 * len(shapes)
     srv.start()
     reqs = [srv.submit(sc, *synth.request_cameras(sc, "preview", 50 + i)) for i, sc in enumerate("ABCA")]
     srv.stop(drain=True)
-    assert {k for s in srv.slots for k in s.rings} == keys
+    st1 = srv.stats()
+    assert st1["captures"] == st0["captures"] and st1["buckets"] == st0["buckets"]
+    assert st1["graph_launches"] == st1["launches"] > 0
     R = capi.Renderer(0)
     fids = {name: R.load(f) for name, f in _fields().items()}
     for r in reqs:

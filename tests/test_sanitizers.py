@@ -17,6 +17,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2311_02542_amd", "csrc")
+from paper_2311_02542_amd.build import SOURCES  # noqa: E402
 ROCM = "/opt/rocm"
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CLANG = os.path.join(ROCM, "llvm", "bin", "clang")
@@ -35,7 +36,7 @@ def sanitized_lib(tmp_path_factory):
     out = tmp_path_factory.mktemp("san")
     lib = str(out / "libvrn_san.so")
     cmd = [HIPCC, *DEVICE_FLAGS, *HOST_SANITIZERS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "capi.cpp"), "-o", lib]
+           *SOURCES, "-o", lib]
     res = subprocess.run(cmd, capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-3000:]
     return out
