@@ -53,7 +53,13 @@ typedef enum {
   VRN_ERR_CANCELLED = -9      /* serving: the request was cancelled */
 } vrn_status;
 
-typedef enum { VRN_F32 = 0, VRN_F16 = 1, VRN_BF16 = 2 } vrn_dtype;
+/* MLP arithmetic (and table storage: VRN_F32 or VRN_F16).  VRN_F32X is FP32
+ * arithmetic computed on the BF16 matrix cores: each FP32 operand is split
+ * exactly into three BF16 parts and six of the nine part products are
+ * accumulated in FP32 (the dropped ones are about 2^-26 of the product,
+ * below FP32 rounding); encoding, transmittance and compositing are FP32 as
+ * in VRN_F32. */
+typedef enum { VRN_F32 = 0, VRN_F16 = 1, VRN_BF16 = 2, VRN_F32X = 3 } vrn_dtype;
 
 /* Everything that defines a field.  Host pointers; copied by vrn_load_field. */
 typedef struct {
@@ -118,7 +124,8 @@ typedef enum {
 } vrn_output;
 
 typedef struct {
-  int32_t compute;            /* a vrn_dtype, the MLP arithmetic: VRN_F32 (FP32 MFMA), VRN_F16 or
+  int32_t compute;            /* a vrn_dtype, the MLP arithmetic: VRN_F32 (FP32 MFMA), VRN_F32X
+                                 (FP32 by split BF16 MFMA), VRN_F16 or
                                  VRN_BF16 (MFMA, FP32 accumulate); march,
                                  transmittance and compositing are FP32 always.
                                  VRN_F16 needs hidden activations within the FP16

@@ -20,8 +20,8 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 VRN_OK, VRN_ERR_INVALID_ARG, VRN_ERR_UNSUPPORTED, VRN_ERR_OUT_OF_MEMORY = 0, -1, -2, -3
 VRN_ERR_BUDGET, VRN_ERR_DEVICE, VRN_ERR_NOT_FOUND, VRN_ERR_BUSY = -4, -5, -6, -7
 VRN_ERR_TIMEOUT, VRN_ERR_CANCELLED = -8, -9
-VRN_F32, VRN_F16, VRN_BF16 = 0, 1, 2
-DTYPES = {"f32": VRN_F32, "f16": VRN_F16, "bf16": VRN_BF16}
+VRN_F32, VRN_F16, VRN_BF16, VRN_F32X = 0, 1, 2, 3
+DTYPES = {"f32": VRN_F32, "f16": VRN_F16, "bf16": VRN_BF16, "f32x": VRN_F32X}
 STATUS_NAMES = {0: "VRN_OK", -1: "VRN_ERR_INVALID_ARG", -2: "VRN_ERR_UNSUPPORTED",
                 -3: "VRN_ERR_OUT_OF_MEMORY", -4: "VRN_ERR_BUDGET", -5: "VRN_ERR_DEVICE",
                 -6: "VRN_ERR_NOT_FOUND", -7: "VRN_ERR_BUSY", -8: "VRN_ERR_TIMEOUT", -9: "VRN_ERR_CANCELLED"}

@@ -126,8 +126,15 @@ uint16_t bf16_bits(float f) {
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 void arrange_weights(const float* W, int L, int nsh, std::vector<float>& w32, std::vector<uint16_t>& w16,
-                     std::vector<uint16_t>& wbf, std::vector<float>& bias) {
+                     std::vector<uint16_t>& wbf, std::vector<uint16_t>& wx3, std::vector<float>& bias) {
   const int din = 2 * L, cin = 15 + nsh;
   // offsets into the concatenated host weights
   const float* W1 = W;
@@ -147,6 +154,7 @@ void arrange_weights(const float* W, int L, int nsh, std::vector<float>& w32, st
   w32.assign(kW32Total, 0.0f);
   w16.assign(kW16Total, 0);
   wbf.assign(kW16Total, 0);
+  wx3.assign(3 * (size_t)kW16Total, 0);
   for (int li = 0; li < 5; ++li) {
     const Layer& Ly = layers[li];
     for (int ot = 0; ot < Ly.n_ot; ++ot)
@@ -160,6 +168,14 @@ void arrange_weights(const float* W, int L, int nsh, std::vector<float>& w32, st
           const size_t o16 = Ly.off + ((size_t)(ot * (Ly.n_k / 8) + s2) * 64 + lane) * 8 + j;
           w16[o16] = f16_bits(v);
           wbf[o16] = bf16_bits(v);
+          // the FP32 weight as the exact sum of three BF16 parts (VRN_F32X):
+          // each part rounds the residual of the previous ones
+          float r = v;
+          for (int k = 0; k < 3; ++k) {
+            const uint16_t b = bf16_bits(r);
+            wx3[(size_t)k * kW16Total + o16] = b;
+            r -= bf16_value(b);
+          }
         }
   }
   bias.assign(kBiasTotal, 0.0f);
@@ -299,8 +315,9 @@ void track(Field* f, hipStream_t s) {
 }
 
 vrn_status check_opts(const vrn_render_opts* opts) {
-  if (opts && opts->compute != VRN_F32 && opts->compute != VRN_F16 && opts->compute != VRN_BF16)
-    return fail(VRN_ERR_INVALID_ARG, "opts.compute must be VRN_F32, VRN_F16 or VRN_BF16");
+  if (opts && opts->compute != VRN_F32 && opts->compute != VRN_F16 && opts->compute != VRN_BF16 &&
+      opts->compute != VRN_F32X)
+    return fail(VRN_ERR_INVALID_ARG, "opts.compute must be VRN_F32, VRN_F16, VRN_BF16 or VRN_F32X");
   if (opts && (opts->output < VRN_OUT_PQ || opts->output > VRN_OUT_SRGB))
     return fail(VRN_ERR_INVALID_ARG, "opts.output must be VRN_OUT_PQ, VRN_OUT_LINEAR or VRN_OUT_SRGB");
   if (opts && (!finite(opts->exposure_ev) || std::fabs(opts->exposure_ev) > 64.0f))
@@ -473,8 +490,8 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
         }
       }
   std::vector<float> w32, bias;
-  std::vector<uint16_t> w16, wbf;
-  arrange_weights(d->weights, (int)L, (int)nsh, w32, w16, wbf, bias);
+  std::vector<uint16_t> w16, wbf, wx3;
+  arrange_weights(d->weights, (int)L, (int)nsh, w32, w16, wbf, wx3, bias);
   std::vector<LevelDev> lv(L);
   for (uint32_t l = 0; l < L; ++l) {
     const uint64_t N = d->level_res[l], s = N + 1;
@@ -487,10 +504,10 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
     P.bz = (P.dense ? (uint32_t)(s * s) : d->hash_primes[2]) * esize;
     const double S = (double)N / (double)d->extent;
     P.s_hi = (float)S;
-    P.s_lo = (float)(S - (double)P.s_hi);
     P.base = (uint32_t)((uint64_t)l * T * esize);
     P.below_n = std::nextafter((float)N, 0.0f);
-    P.pad[0] = P.pad[1] = P.pad[2] = 0u;
+    P.s64 = S;
+    P.top64 = (double)(N - 1);
   }
   // canonical FP32 sample table (same recurrence, same rounding, as the oracle)
   const bool use_table = d->contraction || d->step_growth > 0.0f;
@@ -507,7 +524,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   }
   const uint64_t tab_bytes = n_tab * (d->table_dtype == VRN_F16 ? 2 : 4);
   const uint64_t need = tab_bytes + bricks.size() * 8 + coarse.size() * 8 + (w32.size() + bias.size()) * 4 +
-                        (w16.size() + wbf.size()) * 2 + lv.size() * sizeof(LevelDev) + lat.size() * 4 +
+                        (w16.size() + wbf.size() + wx3.size()) * 2 + lv.size() * sizeof(LevelDev) + lat.size() * 4 +
                         bricks.size() * 4 + 256;
   if (ctx->budget && ctx->used + need > ctx->budget)
     return fail(VRN_ERR_BUDGET, "loading the field would exceed the HBM budget");
@@ -523,12 +540,13 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   float *dw32 = nullptr, *dbias = nullptr, *dlat = nullptr;
   uint32_t *dlist = nullptr, *dcount = nullptr;
   const std::vector<uint32_t> zeros(64, 0u);
-  uint16_t *dw16 = nullptr, *dwbf = nullptr;
+  uint16_t *dw16 = nullptr, *dwbf = nullptr, *dwx3 = nullptr;
   if ((e = upload(f, static_cast<const uint8_t*>(d->tables), tab_bytes, &tab)) ||
       (e = upload(f, lv.data(), lv.size(), &dlv)) || (e = upload(f, bricks.data(), bricks.size(), &dbr)) ||
       (e = upload(f, coarse.data(), coarse.size(), &dco)) ||
       (e = upload(f, coarse_dil.data(), coarse_dil.size(), &dcd)) || (e = upload(f, w32.data(), w32.size(), &dw32)) ||
       (e = upload(f, w16.data(), w16.size(), &dw16)) || (e = upload(f, wbf.data(), wbf.size(), &dwbf)) ||
+      (e = upload(f, wx3.data(), wx3.size(), &dwx3)) ||
       (e = upload(f, bias.data(), bias.size(), &dbias)) ||
       (use_table && (e = upload(f, lat.data(), lat.size(), &dlat))) ||
       (e = alloc_only(f, bricks.size(), &dlist)) || (e = upload(f, zeros.data(), zeros.size(), &dcount)) ||
@@ -547,6 +565,7 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.w32 = dw32;
   F.w16 = dw16;
   F.wbf = dwbf;
+  F.wx3 = dwx3;
   F.bias = dbias;
   F.L = L;
   F.log2T = d->log2_T;
@@ -799,8 +818,8 @@ vrn_status vrn_mlp(vrn_ctx* ctx, vrn_field_id field, const float* d_feat, const 
                    vrn_dtype compute, float* d_sigma, float* d_rgb, void* stream) {
   Range range("vrn_mlp");
   if (!ctx || !d_feat || !d_dir || !d_sigma || !d_rgb) return fail(VRN_ERR_INVALID_ARG, "NULL argument");
-  if (compute != VRN_F32 && compute != VRN_F16 && compute != VRN_BF16)
-    return fail(VRN_ERR_INVALID_ARG, "compute must be VRN_F32, VRN_F16 or VRN_BF16");
+  if (compute != VRN_F32 && compute != VRN_F16 && compute != VRN_BF16 && compute != VRN_F32X)
+    return fail(VRN_ERR_INVALID_ARG, "compute must be VRN_F32, VRN_F16, VRN_BF16 or VRN_F32X");
   std::lock_guard<std::mutex> lock(ctx->mu);
   Field* f = find_field(ctx, field);
   if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");
@@ -821,8 +840,8 @@ vrn_status vrn_prune_grid(vrn_ctx* ctx, vrn_field_id field, float alpha, uint32_
   if (points_per_voxel != 4 && points_per_voxel != 1 && points_per_voxel != 8 && points_per_voxel != 27 &&
       points_per_voxel != 64)
     return fail(VRN_ERR_UNSUPPORTED, "points_per_voxel must be 4 or a cube 1, 8, 27, 64");
-  if (compute != VRN_F32 && compute != VRN_F16 && compute != VRN_BF16)
-    return fail(VRN_ERR_INVALID_ARG, "compute must be VRN_F32, VRN_F16 or VRN_BF16");
+  if (compute != VRN_F32 && compute != VRN_F16 && compute != VRN_BF16 && compute != VRN_F32X)
+    return fail(VRN_ERR_INVALID_ARG, "compute must be VRN_F32, VRN_F16, VRN_BF16 or VRN_F32X");
   std::lock_guard<std::mutex> lock(ctx->mu);
   Field* f = find_field(ctx, field);
   if (!f) return fail(VRN_ERR_NOT_FOUND, "unknown field id");

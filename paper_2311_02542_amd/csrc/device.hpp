@@ -575,35 +575,18 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
 // Hash encoding with LOD (Sec. 4 after iNGP; Sec. 4.2.1 Eq. 3; App. D)
 // ---------------------------------------------------------------------------
 
-// Exact a - b as hi + lo (Knuth two-sum).
-__device__ __forceinline__ void two_diff(float a, float b, float& hi, float& lo) {
-  const float s = a - b;
-  const float ap = s + b;
-  const float bp = s - ap;
-  lo = (a - ap) + (-b - bp);
-  hi = s;
-}
-
-// Base lattice corner and fraction of p = u * S computed as a double-float
-// (u = uh + ul exact, S = s_hi + s_lo): the fraction is accurate to one
-// rounding even at 2e4-cell levels.  When ph alone rounds onto the integer
-// above (below) the true p, the low part makes the fraction negative (>= 1);
-// floor(f) moves the corner to the cell that really contains p, otherwise
-// the interpolation would extrapolate from the neighbouring cell.  The
-// corner is then clamped to [0, N-1] with the fraction carrying the rest
-// (so p = N gives the last cell with fraction 1).
-__device__ __forceinline__ uint32_t base_corner(float uh, float ul, float shi, float slo, float top, float& fr) {
-  const float ph = uh * shi;
-  const float pe = fmaf(uh, shi, -ph);
-  const float pl = pe + (uh * slo + ul * shi);
-  const float fi = floorf(ph);
-  float f = (ph - fi) + pl;
-  const float df = floorf(f);
-  const float ip = fi + df;
-  f = f - df;
-  const float ipc = __builtin_amdgcn_fmed3f(ip, 0.0f, top);
-  fr = f + (ip - ipc);
-  return (uint32_t)ipc;
+// Base lattice corner and fraction of p = u S in FP64 (u = x - aabb_min,
+// exact in FP64 for FP32 x; S = N / extent rounded once), so the fraction
+// is accurate to one FP32 rounding even at 2e4-cell levels, where an FP32 p
+// would carry an error of 1e-3 cells.  FP64 multiply, floor, min/max and
+// conversions issue at the FP32 rate on CDNA.  The corner is clamped to
+// [0, N-1] with the fraction carrying the rest (p = N gives the last cell
+// with fraction 1).
+__device__ __forceinline__ uint32_t base_corner_f64(double u, double s, double top, float& fr) {
+  const double p = u * s;
+  const double ip = fmin(fmax(floor(p), 0.0), top);
+  fr = (float)(p - ip);
+  return (uint32_t)ip;
 }
 
 // Buffer resource over the whole [L][T][2] table (32-bit byte offsets;
@@ -658,16 +641,17 @@ __device__ __forceinline__ void corner_offsets(const FieldDev& F, const LevelDev
 // Levels with LOD weight 0 are not fetched.  feat[2j + f] = level g + 4j,
 // feature f.  dense_mask (bit l: level l is stored densely) lets a group of
 // four levels that is all hashed (or all dense) use one index formula.
-// PRECISE selects the double-float lattice coordinate (FP32 path and the
-// encode stage entry point).
+// PRECISE selects the FP64 lattice coordinate (FP32 paths and the encode
+// stage entry point).
 template <bool TAB16, bool PRECISE>
 __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* lv, __amdgpu_buffer_rsrc_t tab,
                                              const float x[3], float lstar, bool active, int g, float feat[8],
                                              uint32_t& fetches) {
-  float uh[3], ul[3];
+  float uh[3];
+  double ud[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if constexpr (PRECISE) two_diff(x[a], F.amin[a], uh[a], ul[a]);
+    if constexpr (PRECISE) ud[a] = (double)x[a] - (double)F.amin[a];
     else uh[a] = x[a] - F.amin[a];
   }
 #pragma unroll
@@ -683,7 +667,7 @@ __device__ __forceinline__ void encode_point(const FieldDev& F, const LevelDev* 
     uint32_t i0[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if constexpr (PRECISE) i0[a] = base_corner(uh[a], ul[a], P.s_hi, P.s_lo, P.top, fr[a]);
+      if constexpr (PRECISE) i0[a] = base_corner_f64(ud[a], P.s64, P.top64, fr[a]);
       else i0[a] = base_corner_fast(uh[a], P.s_hi, P.below_n, fr[a]);
     }
     uint32_t off[8];
@@ -1189,6 +1173,120 @@ __device__ __forceinline__ void mlp_batch_16(const uint4* __restrict__ sw, const
       lg[t][1] = c3[t][1];
       lg[t][2] = c3[t][2];
     }
+}
+
+// ---------------------------------------------------------------------------
+// FP32-accurate MLP on the BF16 MFMA (VRN_F32X).  Every FP32 operand is the
+// exact sum of three BF16 parts, x = x0 + x1 + x2: each part is the
+// residual of the previous ones rounded to the nearest BF16.  The residuals
+// are exact in FP32 (Sterbenz), and the last holds at most 7 significant
+// bits, so it is exact in BF16 too.  A product x w keeps the six part
+// products whose orders sum to at most 2; the dropped ones (x1 w2, x2 w1,
+// x2 w2) total about 2^-26 |x w|, below FP32's own rounding of the product.
+// BF16 products are exact in FP32 and the MFMA accumulates in FP32, so the
+// layer matches FP32 arithmetic to within its rounding, at the BF16 MFMA
+// rate (six 16x16x32 steps in place of eight 16x16x4 FP32 ones per 32-deep
+// step), and the BF16 MFMA co-executes with VALU work where the FP32 one
+// does not.  Weights are split on the host into the BF16 fragment layout:
+// [part][kW16Total].
+// ---------------------------------------------------------------------------
+struct Bf3 {
+  v8bf p[3];
+};
+
+__device__ __forceinline__ Bf3 split_bf3(const float* v) {
+  Bf3 s;
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = v[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const __bf16 b = (__bf16)r[i];
+      s.p[k][i] = b;
+      if (k < 2) r[i] = r[i] - (float)b;
+    }
+  return s;
+}
+
+__device__ __forceinline__ v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// c + W x over one 32-deep step, the smallest part products first.
+__device__ __forceinline__ v4f mfma_bf3(const Bf3& w, const Bf3& x, v4f c) {
+  c = mfma_bf16(w.p[1], x.p[1], c);
+  c = mfma_bf16(w.p[2], x.p[0], c);
+  c = mfma_bf16(w.p[0], x.p[2], c);
+  c = mfma_bf16(w.p[1], x.p[0], c);
+  c = mfma_bf16(w.p[0], x.p[1], c);
+  return mfma_bf16(w.p[0], x.p[0], c);
+}
+
+// The three parts of weight fragment idx of a layer (offset off16 in the
+// BF16 fragment layout; the parts lie `stride` 16-bit values apart).
+__device__ __forceinline__ Bf3 wfrag_bf3(const uint4* __restrict__ sw3, int stride, int off16, int idx, int lane) {
+  Bf3 w;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint4 u = sw3[(k * stride + off16) / 8 + idx * 64 + lane];
+    __builtin_memcpy(&w.p[k], &u, 16);
+  }
+  return w;
+}
+
+// The same layers, in the same register layouts, as mlp_tile_f32; the
+// color output layer (64 -> 3) runs on the VALU in FP32 from the FP32 C3
+// fragments (sw_c3 = the kW32_C3 block).
+__device__ __forceinline__ void mlp_tile_x3(const uint4* __restrict__ sw3, const float4* __restrict__ sw_c3,
+                                            const float* __restrict__ sb, const float feat[8], const float shs[4],
+                                            int lane, float& o0, float lg[3]) {
+  const int g = lane >> 4;
+  const Bf3 xin = split_bf3(feat);
+  float hv[16];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    const v4f h = relu4(mfma_bf3(wfrag_bf3(sw3, kW16Total, kW16_D1, ot, lane), xin, bias_acc(sb, kB1 + 16 * ot, g)));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = h[r];
+  }
+  v4f o = mfma_bf3(wfrag_bf3(sw3, kW16Total, kW16_D2, 0, lane), split_bf3(hv), zero4());
+  o = mfma_bf3(wfrag_bf3(sw3, kW16Total, kW16_D2, 1, lane), split_bf3(hv + 8), o);
+  o = add_bias4(o, sb, kB2, g);
+  const float cin[8] = {o[0], o[1], o[2], o[3], shs[0], shs[1], shs[2], shs[3]};
+  const Bf3 cv = split_bf3(cin);
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    const v4f c = relu4(mfma_bf3(wfrag_bf3(sw3, kW16Total, kW16_C1, ot, lane), cv, bias_acc(sb, kB3 + 16 * ot, g)));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = c[r];
+  }
+  const Bf3 a0 = split_bf3(hv), a1 = split_bf3(hv + 8);
+  v4f c2[4];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    const v4f c = mfma_bf3(wfrag_bf3(sw3, kW16Total, kW16_C2, 2 * ot, lane), a0, bias_acc(sb, kB4 + 16 * ot, g));
+    c2[ot] = relu4(mfma_bf3(wfrag_bf3(sw3, kW16Total, kW16_C2, 2 * ot + 1, lane), a1, c));
+  }
+  float p[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4 w = sw_c3[it * 64 + 16 * g + c];
+      p[c] = fmaf(w.x, c2[it][0], p[c]);
+      p[c] = fmaf(w.y, c2[it][1], p[c]);
+      p[c] = fmaf(w.z, c2[it][2], p[c]);
+      p[c] = fmaf(w.w, c2[it][3], p[c]);
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    p[c] += __shfl_xor(p[c], 16);
+    p[c] += __shfl_xor(p[c], 32);
+    lg[c] = p[c] + sb[kB5 + c];
+  }
+  o0 = o[0];
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ constexpr int kBlock = 256;         // threads per render block (4 waves)
 // every ray's 16 SH values in FP32 (64 KiB) at the 4 waves/SIMD its registers
 // allow.
 constexpr int kBlockF32 = 1024;
-inline int render_block_threads(int compute) { return compute == 0 ? kBlockF32 : kBlock; }
+inline int render_block_threads(int compute) { return (compute == 0 || compute == 3) ? kBlockF32 : kBlock; }
 constexpr int kHidden = 64;
 constexpr int kCoarseWords = 1024;  // <= 32^3 bits of coarse occupancy in LDS
 constexpr int kMlpBatch = 1;        // 16-sample tiles per 16-bit MLP call (weights read once per call)
@@ -37,11 +37,13 @@ struct LevelDev {
   uint32_t dense;    // 1: index = x + y s + z s^2 with s = N + 1
   uint32_t bx, by, bz;  // per-axis multipliers times the entry size in bytes: (1, s, s^2) dense,
                         // hash primes otherwise (products taken mod 2^32)
-  float s_hi, s_lo;  // N / extent as an unevaluated sum of two floats
+  float s_hi;        // N / extent in FP32 (16-bit paths)
   uint32_t base;     // byte offset of the level's table
   float below_n;     // largest float below N (clamp of the lattice coordinate, 16-bit paths)
-  uint32_t pad[3];
+  double s64;        // N / extent in FP64 (FP32 paths)
+  double top64;      // N - 1 in FP64
 };
+static_assert(sizeof(LevelDev) == 48, "LevelDev is three 16-byte LDS rows");
 
 struct FieldDev {
   const void* tables;        // [L][T][2] fp32 or fp16
@@ -53,6 +55,7 @@ struct FieldDev {
   const float* w32;          // kW32Total
   const uint16_t* w16;       // kW16Total fp16 bits
   const uint16_t* wbf;       // kW16Total bf16 bits
+  const uint16_t* wx3;       // [3][kW16Total] bf16 bits: the exact three-part split of the FP32 weights
   const float* bias;         // kBiasTotal
   uint32_t L, log2T, Tmask, table_f16;
   uint32_t bmask;            // Tmask times the entry size in bytes (hash mask on byte offsets)

@@ -42,23 +42,40 @@ __device__ __forceinline__ float comp_exp(float z) {
 template <bool FAST>
 __device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + comp_exp<FAST>(-z)); }
 
+// MLP arithmetic of a compute mode: 0 FP32 MFMA, 1 FP16, 2 BF16, 3 FP32 by
+// split BF16 (VRN_F32X).  Modes 0 and 3 share everything but the MLP: the
+// FP32 encode, FP32 SH values and the library exp in compositing.
+template <int MODE>
+constexpr bool kF32Class = MODE == 0 || MODE == 3;
+
+// Bytes of the split weights of mode 3 in LDS: three BF16 parts, then the
+// FP32 fragments of the color output layer (run on the VALU).
+constexpr int kX3Bytes = 3 * kW16Total * 2;
+
 template <int MODE>
 struct WeightSmem {
-  static constexpr int kBytes = (MODE == 0) ? kW32Total * 4 : kW16Total * 2;
+  static constexpr int kBytes =
+      (MODE == 0) ? kW32Total * 4 : (MODE == 3 ? kX3Bytes + (kW32Total - kW32_C3) * 4 : kW16Total * 2);
 };
 
 template <int MODE>
 __device__ __forceinline__ const uint4* weight_src(const FieldDev& F) {
   if constexpr (MODE == 0) return reinterpret_cast<const uint4*>(F.w32);
   else if constexpr (MODE == 1) return reinterpret_cast<const uint4*>(F.w16);
-  else return reinterpret_cast<const uint4*>(F.wbf);
+  else if constexpr (MODE == 2) return reinterpret_cast<const uint4*>(F.wbf);
+  else return reinterpret_cast<const uint4*>(F.wx3);
 }
 
 template <int MODE>
 __device__ __forceinline__ void load_weights(const FieldDev& F, uint8_t* s_w, float* s_b) {
   const uint4* src = weight_src<MODE>(F);
   uint4* dst = reinterpret_cast<uint4*>(s_w);
-  for (int i = threadIdx.x; i < WeightSmem<MODE>::kBytes / 16; i += blockDim.x) dst[i] = src[i];
+  constexpr int kMain = MODE == 3 ? kX3Bytes : WeightSmem<MODE>::kBytes;
+  for (int i = threadIdx.x; i < kMain / 16; i += blockDim.x) dst[i] = src[i];
+  if constexpr (MODE == 3) {
+    const uint4* c3 = reinterpret_cast<const uint4*>(F.w32 + kW32_C3);
+    for (int i = threadIdx.x; i < (kW32Total - kW32_C3) / 4; i += blockDim.x) dst[kX3Bytes / 16 + i] = c3[i];
+  }
   for (int i = threadIdx.x; i < kBiasTotal; i += blockDim.x) s_b[i] = F.bias[i];
 }
 
@@ -68,6 +85,9 @@ __device__ __forceinline__ void run_mlp(const uint8_t* s_w, const float* s_b, co
                                         float lg[3]) {
   if constexpr (MODE == 0)
     mlp_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, shs, lane, o0, lg);
+  else if constexpr (MODE == 3)
+    mlp_tile_x3(reinterpret_cast<const uint4*>(s_w), reinterpret_cast<const float4*>(s_w + kX3Bytes), s_b, feat,
+                shs, lane, o0, lg);
   else
     mlp_tile_16<MODE == 2>(reinterpret_cast<const uint4*>(s_w), s_b, feat, Half8<MODE == 2>::pack4(shs), lane,
                            o0, lg);
@@ -139,9 +159,9 @@ __device__ __forceinline__ void store_ray_sh(const FieldDev& F, const Ray& r, ui
 #endif
 
 template <bool TAB16, int MODE, int GEO>
-__global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN_WAVES16) void render_kernel(
+__global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MODE> ? 4 : VRN_WAVES16) void render_kernel(
     RenderArgs A) {
-  constexpr int kThreads = MODE == 0 ? kBlockF32 : kBlock;
+  constexpr int kThreads = kF32Class<MODE> ? kBlockF32 : kBlock;
   __shared__ __align__(16) uint8_t s_w[WeightSmem<MODE>::kBytes];
   __shared__ float s_b[kBiasTotal];
   __shared__ LevelDev s_lv[kMaxLevels];
@@ -150,7 +170,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
   __shared__ uint32_t s_rb[kMaxCams], s_re[kMaxCams];
   __shared__ uint32_t s_stats[6];
   // per-ray SH values: FP32 [lane][g] float4 (FP32 path) or packed 16-bit [lane][g] uint2
-  __shared__ __align__(16) uint8_t s_sh_raw[kThreads * 4 * (MODE == 0 ? 16 : 8)];
+  __shared__ __align__(16) uint8_t s_sh_raw[kThreads * 4 * (kF32Class<MODE> ? 16 : 8)];
   uint2* s_sh = reinterpret_cast<uint2*>(s_sh_raw);
   float4* s_sh4 = reinterpret_cast<float4*>(s_sh_raw);
   __shared__ uint32_t s_slot[kThreads];
@@ -247,7 +267,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
           const uint32_t row = s_rb[c] + ty * kTile + within / kTile;
           if (col < A.W && row < s_re[c]) {
             setup_ray<GEO>(F, A.cams[c], col, row, r);
-            if constexpr (MODE != 0) store_ray_sh<MODE == 2>(F, r, &s_sh[threadIdx.x * 4]);
+            if constexpr (!kF32Class<MODE>) store_ray_sh<MODE == 2>(F, r, &s_sh[threadIdx.x * 4]);
             else store_ray_sh_f32(F, r, &s_sh4[threadIdx.x * 4]);
             pix = (c * A.H + row) * A.W + col;
             T = 1.0f;
@@ -290,7 +310,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
 
     // ---- 3. encode + MLP of the compacted samples -------------------------
     float so0 = 0.0f, sl0 = 0.0f, sl1 = 0.0f, sl2 = 0.0f;
-    if constexpr (MODE == 0) {
+    if constexpr (kF32Class<MODE>) {
       for (int t = 0; t < nt; ++t) {
         asm volatile("" ::: "memory");
         bool act;
@@ -305,7 +325,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
           shs[3] = v.w;
         }
         float o0, lg[3];
-        mlp_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, shs, lane, o0, lg);
+        run_mlp<MODE>(s_w, s_b, F, feat, shs, lane, o0, lg);
         const int from = rank & 15;
         const float a0 = shfl_f(o0, from), a1 = shfl_f(lg[0], from);
         const float a2 = shfl_f(lg[1], from), a3 = shfl_f(lg[2], from);
@@ -369,7 +389,7 @@ __global__ __launch_bounds__(MODE == 0 ? kBlockF32 : kBlock, MODE == 0 ? 4 : VRN
     // ---- 4. composite (FP32), terminate --------------------------------
     if (has) {
       VRN_DEBUG_COUNT(so0 != so0 || sl0 != sl0 || sl1 != sl1 || sl2 != sl2, kDbgMlpNaN);
-      constexpr bool kFast = MODE != 0;
+      constexpr bool kFast = !kF32Class<MODE>;
       const float sd = comp_exp<kFast>(so0) * sdt;
       const float trans = comp_exp<kFast>(-sd);
       const float wgt = T * (1.0f - trans);
@@ -648,11 +668,29 @@ __device__ __forceinline__ float density_tile_16(const uint4* __restrict__ sw, c
   return o[0];
 }
 
+// Density layers by split BF16 (mode 3): the D1 and D2 fragments of each
+// of the three parts, staged [part][kW16_C1].
+__device__ __forceinline__ float density_tile_x3(const uint4* __restrict__ sw3, const float* __restrict__ sb,
+                                                 const float feat[8], int lane) {
+  const int g = lane >> 4;
+  const Bf3 xin = split_bf3(feat);
+  float hv[16];
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) {
+    const v4f h = relu4(mfma_bf3(wfrag_bf3(sw3, kW16_C1, kW16_D1, ot, lane), xin, bias_acc(sb, kB1 + 16 * ot, g)));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hv[4 * ot + r] = h[r];
+  }
+  v4f o = mfma_bf3(wfrag_bf3(sw3, kW16_C1, kW16_D2, 0, lane), split_bf3(hv), zero4());
+  o = mfma_bf3(wfrag_bf3(sw3, kW16_C1, kW16_D2, 1, lane), split_bf3(hv + 8), o);
+  return o[0] + sb[kB2 + 4 * g];
+}
+
 // The density-layer weights (D1 and D2) are the first kW32_C1 / kW16_C1
-// elements of each weight form.
+// elements of each weight form (of each of the three parts in mode 3).
 template <int MODE>
 struct DensitySmem {
-  static constexpr int kBytes = (MODE == 0) ? kW32_C1 * 4 : kW16_C1 * 2;
+  static constexpr int kBytes = (MODE == 0) ? kW32_C1 * 4 : (MODE == 3 ? 3 * kW16_C1 * 2 : kW16_C1 * 2);
 };
 
 constexpr int kPruneQueue = 128;   // per-wave voxel queue: < 64 carried + one brick
@@ -670,7 +708,13 @@ __global__ __launch_bounds__(kBlock) void prune_kernel(FieldDev F, float alpha, 
   {
     const uint4* src = weight_src<MODE>(F);
     uint4* dst = reinterpret_cast<uint4*>(s_w);
-    for (int i = threadIdx.x; i < DensitySmem<MODE>::kBytes / 16; i += blockDim.x) dst[i] = src[i];
+    if constexpr (MODE == 3) {
+      constexpr int kPart = kW16_C1 * 2 / 16;   // uint4 per part
+      for (int i = threadIdx.x; i < 3 * kPart; i += blockDim.x)
+        dst[i] = src[(i / kPart) * (kW16Total * 2 / 16) + i % kPart];
+    } else {
+      for (int i = threadIdx.x; i < DensitySmem<MODE>::kBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
     for (int i = threadIdx.x; i < kBiasTotal; i += blockDim.x) s_b[i] = F.bias[i];
     if (threadIdx.x < F.L) s_lv[threadIdx.x] = F.levels[threadIdx.x];
   }
@@ -729,10 +773,12 @@ __global__ __launch_bounds__(kBlock) void prune_kernel(FieldDev F, float alpha, 
         float feat[8];
         uint32_t fetches = 0;
         // every level weighs 1 (no ray, no LOD): L* above the finest level
-        encode_point<TAB16, MODE == 0>(F, s_lv, tab, x, 1.0e9f, act, g, feat, fetches);
+        encode_point<TAB16, kF32Class<MODE>>(F, s_lv, tab, x, 1.0e9f, act, g, feat, fetches);
         float o0;
         if constexpr (MODE == 0)
           o0 = density_tile_f32(reinterpret_cast<const float4*>(s_w), s_b, F.d1_ksteps / 4, feat, lane);
+        else if constexpr (MODE == 3)
+          o0 = density_tile_x3(reinterpret_cast<const uint4*>(s_w), s_b, feat, lane);
         else
           o0 = density_tile_16<MODE == 2>(reinterpret_cast<const uint4*>(s_w), s_b, feat, lane);
         if (act && g == 0) {
@@ -843,10 +889,12 @@ static int blocks_per_cu_geo(int table_f16, int compute) {
   if (table_f16) {
     if (compute == 0) return blocks_per_cu_impl<true, 0, GEO>();
     if (compute == 1) return blocks_per_cu_impl<true, 1, GEO>();
+    if (compute == 3) return blocks_per_cu_impl<true, 3, GEO>();
     return blocks_per_cu_impl<true, 2, GEO>();
   }
   if (compute == 0) return blocks_per_cu_impl<false, 0, GEO>();
   if (compute == 1) return blocks_per_cu_impl<false, 1, GEO>();
+  if (compute == 3) return blocks_per_cu_impl<false, 3, GEO>();
   return blocks_per_cu_impl<false, 2, GEO>();
 }
 
@@ -859,10 +907,12 @@ static void launch_render_geo(const RenderArgs& a, int compute, dim3 gr, dim3 bl
   if (a.F.table_f16) {
     if (compute == 0) hipLaunchKernelGGL((render_kernel<true, 0, GEO>), gr, bl, 0, s, a);
     else if (compute == 1) hipLaunchKernelGGL((render_kernel<true, 1, GEO>), gr, bl, 0, s, a);
+    else if (compute == 3) hipLaunchKernelGGL((render_kernel<true, 3, GEO>), gr, bl, 0, s, a);
     else hipLaunchKernelGGL((render_kernel<true, 2, GEO>), gr, bl, 0, s, a);
   } else {
     if (compute == 0) hipLaunchKernelGGL((render_kernel<false, 0, GEO>), gr, bl, 0, s, a);
     else if (compute == 1) hipLaunchKernelGGL((render_kernel<false, 1, GEO>), gr, bl, 0, s, a);
+    else if (compute == 3) hipLaunchKernelGGL((render_kernel<false, 3, GEO>), gr, bl, 0, s, a);
     else hipLaunchKernelGGL((render_kernel<false, 2, GEO>), gr, bl, 0, s, a);
   }
 }
@@ -912,10 +962,12 @@ hipError_t launch_prune(const FieldDev& F, float alpha, uint32_t npts, int compu
   if (F.table_f16) {
     if (compute == 0) launch_prune_mode<true, 0>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
     else if (compute == 1) launch_prune_mode<true, 1>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
+    else if (compute == 3) launch_prune_mode<true, 3>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
     else launch_prune_mode<true, 2>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
   } else {
     if (compute == 0) launch_prune_mode<false, 0>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
     else if (compute == 1) launch_prune_mode<false, 1>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
+    else if (compute == 3) launch_prune_mode<false, 3>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
     else launch_prune_mode<false, 2>(F, alpha, npts, p, list, cnt, bits_out, max_op, n_cu, s);
   }
   return hipGetLastError();
@@ -1026,6 +1078,7 @@ hipError_t launch_mlp(const FieldDev& F, const float* feat, const float* dir, ui
   const dim3 gr((unsigned)(((uint64_t)n + per_block - 1) / per_block)), bl(kBlock);
   if (compute == 0) hipLaunchKernelGGL((mlp_kernel<0>), gr, bl, 0, s, F, feat, dir, n, sigma, rgb);
   else if (compute == 1) hipLaunchKernelGGL((mlp_kernel<1>), gr, bl, 0, s, F, feat, dir, n, sigma, rgb);
+  else if (compute == 3) hipLaunchKernelGGL((mlp_kernel<3>), gr, bl, 0, s, F, feat, dir, n, sigma, rgb);
   else hipLaunchKernelGGL((mlp_kernel<2>), gr, bl, 0, s, F, feat, dir, n, sigma, rgb);
   return hipGetLastError();
 }

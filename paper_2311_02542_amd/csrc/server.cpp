@@ -461,7 +461,8 @@ void loop(vrn_server* sv) {
 }
 
 bool valid_render_opts(const vrn_render_opts& o) {
-  return (o.compute == VRN_F32 || o.compute == VRN_F16 || o.compute == VRN_BF16) && o.output >= VRN_OUT_PQ &&
+  return (o.compute == VRN_F32 || o.compute == VRN_F16 || o.compute == VRN_BF16 || o.compute == VRN_F32X) &&
+         o.output >= VRN_OUT_PQ &&
          o.output <= VRN_OUT_SRGB && std::isfinite(o.exposure_ev) && std::fabs(o.exposure_ev) <= 64.0f;
 }
 

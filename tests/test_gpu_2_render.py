@@ -34,31 +34,34 @@ def gpu_render(R, field, cams, W, H, compute="f32", linear=False, fid=None):
     return rgba.cpu().numpy(), ns.cpu().numpy()
 
 
-def test_blobs64_whole_images(R):
+@pytest.mark.parametrize("compute", ["f32", "f32x"])
+def test_blobs64_whole_images(R, compute):
     f = synth.field_blobs64()
     cams = synth.cameras_blobs64(6)
-    rgba, ns = gpu_render(R, f, cams, 64, 64)
+    rgba, ns = gpu_render(R, f, cams, 64, 64, compute)
     ref = render_fp64(f, cams, 64, 64)
     mx, mean, ties = compare_render(rgba, ns, ref, TOL)
-    print(f"c1 max {mx:.3g} mean {mean:.3g} ties {ties}")
+    print(f"c1 {compute} max {mx:.3g} mean {mean:.3g} ties {ties}")
     assert mx <= TOL
 
 
-def test_room256_whole_image_ragged(R):
+@pytest.mark.parametrize("compute", ["f32", "f32x"])
+def test_room256_whole_image_ragged(R, compute):
     f = synth.field_room256()
     cams = synth.cameras_room256(2, 100, 77)     # 13 x 10 tiles with ragged edges
-    rgba, ns = gpu_render(R, f, cams, 100, 77)
+    rgba, ns = gpu_render(R, f, cams, 100, 77, compute)
     ref = render_fp64(f, cams, 100, 77)
     mx, mean, ties = compare_render(rgba, ns, ref, TOL)
-    print(f"c2 small max {mx:.3g} mean {mean:.3g} ties {ties}")
+    print(f"c2 small {compute} max {mx:.3g} mean {mean:.3g} ties {ties}")
     assert mx <= TOL
     assert ref["n"].sum() > 5000
 
 
-def test_room256_full_size_sampled(R):
+@pytest.mark.parametrize("compute", ["f32", "f32x"])
+def test_room256_full_size_sampled(R, compute):
     f = synth.field_room256()
     cams = synth.cameras_room256(1)
-    rgba, ns = gpu_render(R, f, cams, 1024, 1024)
+    rgba, ns = gpu_render(R, f, cams, 1024, 1024, compute)
     rng = np.random.default_rng(3)
     px = np.stack([np.zeros(1500, int), rng.integers(0, 1024, 1500), rng.integers(0, 1024, 1500)], 1)
     ref = render_fp64(f, cams, 1024, 1024, pixels=px)
@@ -68,17 +71,18 @@ def test_room256_full_size_sampled(R):
     assert mx <= TOL
 
 
-def test_house_stereo_full_size_sampled_fp32(R):
+@pytest.mark.parametrize("compute", ["f32", "f32x"])
+def test_house_stereo_full_size_sampled_fp32(R, compute):
     f = synth.field_house512(table_dtype=np.float32)
     cams = synth.cameras_house_stereo([0])[0]
-    rgba, ns = gpu_render(R, f, cams, 2048, 2048)
+    rgba, ns = gpu_render(R, f, cams, 2048, 2048, compute)
     rng = np.random.default_rng(4)
     m = 300
     px = np.stack([rng.integers(0, 2, m), rng.integers(0, 2048, m), rng.integers(0, 2048, m)], 1)
     ref = render_fp64(f, cams, 2048, 2048, pixels=px)
     sel = (px[:, 0] * 2048 + px[:, 1]) * 2048 + px[:, 2]
     mx, mean, ties = compare_render(rgba.reshape(-1, 4)[sel], ns.reshape(-1)[sel], ref, TOL)
-    print(f"c4 stereo sampled max {mx:.3g} mean {mean:.3g} ties {ties}")
+    print(f"c4 stereo {compute} sampled max {mx:.3g} mean {mean:.3g} ties {ties}")
     assert mx <= TOL
     assert ref["n"].sum() > 0
 

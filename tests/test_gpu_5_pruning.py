@@ -66,7 +66,7 @@ def test_prune_room256_sampled(R):
     assert 0 < g.sum() < sample.size
 
 
-@pytest.mark.parametrize("compute", ["f32", "f16"])
+@pytest.mark.parametrize("compute", ["f32", "f32x", "f16"])
 def test_prune_house512_sampled(R, compute):
     """The timed pruning workload's field (house, 512^3, FP16 tables, 4
     points per voxel) at full size, checked on 3,000 sampled occupied voxels.
@@ -89,7 +89,7 @@ def test_prune_house512_sampled(R, compute):
     o = ref_mx[sample] >= alpha
     err = np.abs(mx[sample] - ref_mx[sample])
     print(f"house512 {compute}: max opacity error {err.max():.3g}, kept {g.sum()} of {sample.size}")
-    if compute == "f32":
+    if compute in ("f32", "f32x"):
         np.testing.assert_allclose(mx[sample], ref_mx[sample], rtol=1e-5)
         assert not ((g != o) & ~tie[sample]).any()
     else:
