@@ -211,11 +211,12 @@ def test_maximum_cameras_and_table_size(R, table_dtype):
 
 
 @pytest.mark.parametrize("variant", ["sh1_L5", "sh3_bias", "radius_tmin", "f16tables_f32mlp", "f32tables_bf16mlp",
-                                     "nonzero_biases"])
+                                     "nonzero_biases", "large_x_prime", "large_x_prime_f16"])
 def test_field_parameter_variants(R, variant):
     """Field parameters the benchmark workloads leave at one value: SH bands 1 and 3, an
     odd level count, LOD bias and radius scale, a loose t_min, nonzero hidden
-    biases, and the mixed table/MLP precisions.  FP32-MLP renders within 1e-5
+    biases, the mixed table/MLP precisions, and a hash whose x prime is not 1
+    (the full 32-bit multiply of the x coordinate).  FP32-MLP renders within 1e-5
     PQ with bit-exact counts; 16-bit MLPs within the precision budget."""
     rng = np.random.default_rng(77)
     g = 32
@@ -231,7 +232,12 @@ def test_field_parameter_variants(R, variant):
         kw.update(table_dtype=np.float16)
     elif variant == "f32tables_bf16mlp":
         compute = "bf16"
+    elif variant == "large_x_prime_f16":
+        kw.update(table_dtype=np.float16)
+        compute = "f16"
     f = tiny_field(g, occ, (-0.5, -0.5, -0.5), 1.0, **kw)
+    if variant.startswith("large_x_prime"):
+        f["hash_primes"] = np.array([73856093, 19349663, 83492791], np.uint32)
     if variant == "sh3_bias":
         f["lod_bias"] = float(F32(-0.7))
     elif variant == "radius_tmin":
