@@ -29,9 +29,11 @@ scheduling loop and no CPU fallback.
 from __future__ import annotations
 
 import argparse
+import atexit
 import json
 import sys
 import time
+import weakref
 
 import numpy as np
 
@@ -160,6 +162,20 @@ class Request:
         return capi.vrn_server_cancel(self._server.sv, self.rid)
 
 
+# Engines still open at interpreter exit are destroyed while the HIP runtime
+# is intact (their scheduler threads make HIP calls until stopped).
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_servers():
+    for srv in list(_LIVE):
+        try:
+            srv.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Resident fields on one context plus a native serving engine.  The HBM
     budget covers the fields, the slot workspaces and the engine's arena, in
@@ -198,6 +214,7 @@ class Server:
         except capi.VrnError:
             self._free_ctx()
             raise
+        _LIVE.add(self)
 
     # ---------------------------------------------------------------- API
     def out_bytes(self, n_cams, W, H):
@@ -276,6 +293,7 @@ class Server:
         if self.ctx is not None:
             self._free_ctx()
         self.arena = None
+        _LIVE.discard(self)
 
 
 def summarize(reqs, wall_s):

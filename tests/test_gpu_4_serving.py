@@ -353,3 +353,52 @@ def test_held_results_count_against_budget():
     peak = torch.cuda.max_memory_allocated() - base
     assert peak <= budget - srv.field_bytes, (peak, budget - srv.field_bytes)
     srv.close()
+
+
+def test_concurrent_clients():
+    """Four client threads submit, wait for, check and release their own
+    requests at once (the engine's calls are thread-safe): every request
+    completes, keeps its own result until released, and matches a direct
+    render bit for bit."""
+    torch = need_gpu()
+    srv = serve.Server(_fields(), 8 << 30, n_slots=3, compute="f16", use_graphs=True)
+    R = capi.Renderer(0)
+    fids = {name: R.load(f) for name, f in _fields().items()}
+    errors = []
+    lock = threading.Lock()
+
+    def client(seed):
+        rng = np.random.default_rng(seed)
+        try:
+            mine = []
+            for i in range(12):
+                scene = "ABC"[int(rng.integers(3))]
+                kind = ["preview", "tile"][int(rng.integers(2))]
+                cams, W, H = synth.request_cameras(scene, kind, int(rng.integers(1 << 30)))
+                mine.append(srv.submit(scene, cams, W, H))
+            for r in mine:
+                assert r.done.wait(60) and r.error is None, r.error
+            for r in mine[:3]:
+                with lock:
+                    ref, ref_n = R.render(fids[r.scene], r.cams, r.W, r.H, "f16")
+                    torch.cuda.synchronize()
+                    assert torch.equal(ref, r.result[0]) and torch.equal(ref_n, r.result[1])
+            for r in mine:
+                r.release()
+        except Exception as e:          # reported by the main thread
+            errors.append(e)
+
+    srv.start()
+    threads = [threading.Thread(target=client, args=(100 + k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    srv.stop(drain=True)
+    st = srv.stats()
+    for fid in fids.values():
+        R.unload(fid)
+    R.close()
+    srv.close()
+    assert not errors, errors
+    assert st["completed"] == 48 and st["requests"] == 0 and st["held_bytes"] == 0
