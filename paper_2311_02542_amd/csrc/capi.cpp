@@ -593,6 +593,23 @@ vrn_status vrn_load_field(vrn_ctx* ctx, const vrn_field_desc* d, vrn_field_id* o
   F.d1_ksteps = L > 8 ? 8u : 4u;
   F.lat = dlat;
   F.lat_K = use_table ? d->max_lattice : 0u;
+  // the table's shape, for the search guess: steps of dt while step_growth
+  // t_k <= dt, growth by (1 + step_growth) per step after
+  F.step_growth = d->step_growth;
+  F.lat_tsw = INFINITY;
+  F.lat_ksw = 0.0f;
+  F.lat_inv_log = 0.0f;
+  if (use_table && d->step_growth > 0.0f) {
+    for (uint32_t k = 0; k < d->max_lattice; ++k) {
+      const float g = d->step_growth * lat[k];
+      if (g > d->dt) {
+        F.lat_tsw = lat[k];
+        F.lat_ksw = (float)k;
+        break;
+      }
+    }
+    F.lat_inv_log = (float)(1.0 / std::log1p((double)d->step_growth));
+  }
   F.contract = d->contraction;
   for (int a = 0; a < 3; ++a) F.center[a] = d->center[a];
   F.radius = d->contraction ? d->radius : 1.0f;

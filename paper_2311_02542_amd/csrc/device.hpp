@@ -75,9 +75,28 @@ __device__ __forceinline__ float cone_pitch(const vrn_camera& c, const float w[3
   return scale * sn * __builtin_amdgcn_rsqf(0.5f * (1.0f + cs));
 }
 
-// Number of table entries <= t (binary search over the canonical FP32 table).
+// Number of lattice samples k < K whose canonical table entry t_k is <= t.
+// The table's shape gives a guess -- steps of dt up to t_sw, then growth by
+// (1 + g) per step -- that the FP32 recurrence departs from by a fraction
+// of a step on the tables used here; a walk over neighbouring entries (two
+// independent loads per step) makes it exact, and a binary search takes
+// over if the walk runs long.  The plain binary search costs ~log2 K
+// dependent loads on every skip of the march.
 __device__ __forceinline__ int table_count_le(const FieldDev& F, float t) {
-  int lo = 0, hi = (int)F.lat_K;   // answer in [lo, hi]
+  const int K = (int)F.lat_K;
+  if (!(t >= F.lat[0])) return 0;   // NaN included
+  if (t >= F.lat[K - 1]) return K;
+  // the count is in [1, K - 1]: t_{c-1} <= t < t_c
+  const float kf = t < F.lat_tsw ? (t - 0.5f * F.dt) * F.inv_dt
+                                 : F.lat_ksw + __logf(t / F.lat_tsw) * F.lat_inv_log;
+  int c = (int)fminf(fmaxf(kf + 1.0f, 1.0f), (float)(K - 1));
+  for (int i = 0; i < 6; ++i) {
+    const float a = F.lat[c - 1], b = F.lat[c];
+    if (a > t) --c;
+    else if (b <= t) ++c;
+    else return c;
+  }
+  int lo = 1, hi = K - 1;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (F.lat[mid] <= t) lo = mid + 1;
@@ -203,13 +222,18 @@ __device__ __forceinline__ void contract_point(const FieldDev& F, float x[3]) {
   }
 }
 
-// Canonical lattice sample k: t = (k + .5) dt (or the FP32 table entry),
-// x = o + t d (contracted for unbounded fields), q = (x - amin) cs.
+// The table entry after t: the same FP32 recurrence, in the same operation
+// order, that built the table on the host (t_{k+1} = t_k + max(dt, g t_k)),
+// so table_next(t_k) equals t_{k+1} bit for bit.
+__device__ __forceinline__ float table_next(const FieldDev& F, float t) {
+  const float g = F.step_growth * t;
+  return t + (g > F.dt ? g : F.dt);
+}
+
+// Canonical position of the lattice sample at parameter t: x = o + t d
+// (contracted for unbounded fields), q = (x - amin) cs.
 template <int GEO>
-__device__ __forceinline__ void lattice_q(const FieldDev& F, const Ray& r, int k, float& t, float x[3],
-                                          float q[3]) {
-  if constexpr (GEO == 0) t = ((float)k + 0.5f) * F.dt;
-  else t = F.lat[k];
+__device__ __forceinline__ void lattice_pos(const FieldDev& F, const Ray& r, float t, float x[3], float q[3]) {
   x[0] = r.ox + t * r.dx;
   x[1] = r.oy + t * r.dy;
   x[2] = r.oz + t * r.dz;
@@ -218,6 +242,15 @@ __device__ __forceinline__ void lattice_q(const FieldDev& F, const Ray& r, int k
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) q[a] = (x[a] - F.amin[a]) * F.cs;
+}
+
+// Canonical lattice sample k: t = (k + .5) dt (or the FP32 table entry).
+template <int GEO>
+__device__ __forceinline__ void lattice_q(const FieldDev& F, const Ray& r, int k, float& t, float x[3],
+                                          float q[3]) {
+  if constexpr (GEO == 0) t = ((float)k + 0.5f) * F.dt;
+  else t = F.lat[k];
+  lattice_pos<GEO>(F, r, t, x, q);
 }
 
 __device__ __forceinline__ int cell_of(float q, int G) {
@@ -309,7 +342,7 @@ __device__ __forceinline__ bool curve_bound(const FieldDev& F, const Ray& r, con
 // in the shrunk box.  Returns true if r.k moved.
 template <int GEO>
 __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float q[3], int ox, int oy, int oz,
-                                         float size) {
+                                         float size, float& t_land) {
   const float lo[3] = {ox * size + r.delta, oy * size + r.delta, oz * size + r.delta};
   const float hi[3] = {(ox + 1) * size - r.delta, (oy + 1) * size - r.delta, (oz + 1) * size - r.delta};
   if (!(q[0] >= lo[0] && q[0] <= hi[0] && q[1] >= lo[1] && q[1] <= hi[1] && q[2] >= lo[2] && q[2] <= hi[2]))
@@ -367,6 +400,7 @@ __device__ __forceinline__ bool skip_box(const FieldDev& F, Ray& r, const float 
     if (q2[0] >= lo[0] && q2[0] <= hi[0] && q2[1] >= lo[1] && q2[1] <= hi[1] && q2[2] >= lo[2] &&
         q2[2] <= hi[2]) {
       r.k = kb + 1;
+      t_land = t2;
       return true;
     }
   }
@@ -475,11 +509,21 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
                                           uint32_t& steps, float& st, float sx[3]) {
   const int G = (int)F.G;
   const float cb = (float)(1u << F.cshift);
+  // sample-table lattices: the parameter of sample r.k is carried from the
+  // previous test (tk, valid while kt == r.k) by the table's own
+  // recurrence, so stepping and box skips read no table entry
+  int kt = -1;
+  float tk = 0.0f;
   for (uint32_t it = 0; it < budget; ++it) {
     if (r.k > r.k_hi) return 2;
     ++steps;
     float t, x[3], q[3];
-    lattice_q<GEO>(F, r, r.k, t, x, q);
+    if constexpr (GEO == 0) {
+      lattice_q<GEO>(F, r, r.k, t, x, q);
+    } else {
+      t = kt == r.k ? tk : F.lat[r.k];
+      lattice_pos<GEO>(F, r, t, x, q);
+    }
     const int cx = cell_of(q[0], G), cy = cell_of(q[1], G), cz = cell_of(q[2], G);
     // empty box to try to jump over: origin (in units of its size) and size
     int bo[3] = {0, 0, 0};
@@ -565,7 +609,22 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
         }
       }
     }
-    const bool moved = bsize > 0.0f && skip_box<GEO>(F, r, q, bo[0], bo[1], bo[2], bsize);
+    float t_land = 0.0f;   // table entries are > 0: 0 means not known
+    const bool moved = bsize > 0.0f && skip_box<GEO>(F, r, q, bo[0], bo[1], bo[2], bsize, t_land);
+    if constexpr (GEO == 1) {
+      // the next test's parameter: the successor of this one, or of the
+      // landing sample of a straight skip (r.k is then already past it);
+      // after a curve skip the next test reads the table
+      if (!moved) {
+        tk = table_next(F, t);
+        kt = r.k + 1;
+      } else if (t_land > 0.0f) {
+        tk = table_next(F, t_land);
+        kt = r.k;
+      } else {
+        kt = -1;
+      }
+    }
     if (!moved) r.k++;
   }
   return 0;
@@ -770,11 +829,12 @@ __device__ __forceinline__ void encode_point_h2(const FieldDev& F, const LevelDe
   }
 }
 
-// Step length of lattice sample k (uniform lattice or FP32 table).
+// Step length of the lattice sample at parameter t (uniform lattice, or
+// the FP32 table: t_{k+1} - t_k, with t_{k+1} from the table's recurrence).
 template <int GEO>
-__device__ __forceinline__ float sample_step(const FieldDev& F, int k) {
+__device__ __forceinline__ float sample_step(const FieldDev& F, float t) {
   if constexpr (GEO == 0) return F.dt;
-  else return F.lat[k + 1] - F.lat[k];
+  else return table_next(F, t) - t;
 }
 
 // L* of a sample of a contracted field: the footprint is the distance between

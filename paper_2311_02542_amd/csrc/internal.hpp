@@ -71,6 +71,10 @@ struct FieldDev {
   // table lattice / contraction (GEO = 1 kernels)
   const float* lat;          // t_0 .. t_K (K + 1 entries), canonical FP32
   uint32_t lat_K;            // number of lattice samples
+  float step_growth;         // table recurrence t_{k+1} = t_k + max(dt, step_growth t_k)
+  float lat_tsw;             // first table entry whose step is the growth term (inf: none)
+  float lat_ksw;             // its index
+  float lat_inv_log;         // 1 / ln(1 + step_growth)
   int32_t contract;          // L-infinity contraction on
   float center[3], inv_radius, radius;
   float lod_c2;              // ln(2 s): LOD constant when the footprint is already normalised

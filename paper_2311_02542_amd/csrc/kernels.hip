@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
       if (mres == 2) retire();
       if (mres == 1) {
         if (F.lod) slst = (GEO == 1 && F.contract) ? level_star_contracted(F, r, st, sx) : level_star(F, st, r.lr);
-        sdt = sample_step<GEO>(F, r.k - 1);
+        sdt = sample_step<GEO>(F, st);
       }
     }
     const bool has = mres == 1;
