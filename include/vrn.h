@@ -440,6 +440,17 @@ double vrn_server_clock(void);
  * counters after reading.  VRN_ERR_UNSUPPORTED in release builds. */
 vrn_status vrn_debug_counters(vrn_ctx* ctx, uint64_t out[6], int reset);
 
+/* Where render waves spend their time, in a library built with
+ * -DVRN_PHASE_TIMING (synchronises the device first): shader clocks
+ * (s_memtime) summed over the waves of every render since the last reset,
+ * per step of a wave's round -- out[0] refill (new rays and their set-up),
+ * out[1] march (with the compaction of the samples found), out[2] encode
+ * (gathering each tile's samples and the hash-grid encode), out[3] MLP,
+ * out[4] return of the MLP results to the rays' lanes, out[5] compositing
+ * (and, once per wave, the block's set-up).  reset != 0 zeroes the sums
+ * after reading.  VRN_ERR_UNSUPPORTED in other builds. */
+vrn_status vrn_phase_cycles(vrn_ctx* ctx, uint64_t out[6], int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vrn_prune_grid": (c_i32, [c_vp, c_u32, c_f, c_u32, c_i32, c_vp, c_vp, c_vp]),
         "vrn_set_occupancy": (c_i32, [c_vp, c_u32, c_vp, c_vp]),
         "vrn_debug_counters": (c_i32, [c_vp, P(c_u64), ctypes.c_int]),
+        "vrn_phase_cycles": (c_i32, [c_vp, P(c_u64), ctypes.c_int]),
         "vrn_server_create": (c_i32, [c_vp, P(VrnServerOpts), P(c_vp)]),
         "vrn_server_destroy": (None, [c_vp]),
         "vrn_server_hold": (c_i32, [c_vp, ctypes.c_int]),
@@ -411,6 +412,18 @@ def vrn_debug_counters(ctx, reset=False) -> dict:
     out = (c_u64 * len(DEBUG_SLOTS))()
     _check(lib.vrn_debug_counters(ctx, out, int(bool(reset))), lib)
     return dict(zip(DEBUG_SLOTS, (int(v) for v in out)))
+
+
+PHASE_SLOTS = ("refill", "march", "encode", "mlp", "return", "composite")
+
+
+def vrn_phase_cycles(ctx, reset=False) -> dict:
+    """Shader clocks per step of the render waves' rounds, from a library
+    built with -DVRN_PHASE_TIMING (raises VRN_ERR_UNSUPPORTED otherwise)."""
+    lib = load_library()
+    out = (c_u64 * len(PHASE_SLOTS))()
+    _check(lib.vrn_phase_cycles(ctx, out, int(bool(reset))), lib)
+    return dict(zip(PHASE_SLOTS, (int(v) for v in out)))
 
 
 def vrn_set_occupancy(ctx, fid, bits, stream=None):

@@ -883,6 +883,19 @@ vrn_status vrn_debug_counters(vrn_ctx* ctx, uint64_t out[6], int reset) {
   return VRN_OK;
 }
 
+vrn_status vrn_phase_cycles(vrn_ctx* ctx, uint64_t out[6], int reset) {
+  if (!ctx || !out) return fail(VRN_ERR_INVALID_ARG, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hipSetDevice(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  unsigned long long v[kPhaseSlots] = {};
+  if (e == hipSuccess) e = phase_cycles(v, reset != 0);
+  if (e == hipErrorNotSupported) return fail(VRN_ERR_UNSUPPORTED, "library built without VRN_PHASE_TIMING");
+  if (e != hipSuccess) return hip_fail(e, "phase cycles");
+  for (int i = 0; i < kPhaseSlots; ++i) out[i] = v[i];
+  return VRN_OK;
+}
+
 vrn_status vrn_set_occupancy(vrn_ctx* ctx, vrn_field_id field, const uint32_t* d_bits, void* stream) {
   Range range("vrn_set_occupancy");
   if (!ctx || !d_bits) return fail(VRN_ERR_INVALID_ARG, "ctx or d_bits is NULL");

@@ -131,6 +131,12 @@ extern __device__ unsigned long long vrn_debug_counts[kDbgSlots];
 // release builds.
 hipError_t debug_counters(unsigned long long out[kDbgSlots], bool reset);
 
+// Phase-timing builds (-DVRN_PHASE_TIMING) sum, over the waves of every
+// render, the shader clocks (s_memtime) each wave spends in each step of its
+// rounds; vrn_phase_cycles reads the sums.  Other builds compile none of it.
+enum PhaseSlot { kPhRefill = 0, kPhMarch, kPhEncode, kPhMlp, kPhReturn, kPhComposite, kPhaseSlots };
+hipError_t phase_cycles(unsigned long long out[kPhaseSlots], bool reset);
+
 hipError_t launch_render(const RenderArgs& a, int compute, int grid, hipStream_t s);
 int render_blocks_per_cu(const FieldDev& F, int compute);
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t s);

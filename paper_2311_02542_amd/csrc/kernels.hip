@@ -30,6 +30,34 @@ __device__ unsigned long long vrn_debug_counts[kDbgSlots];
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
+#ifdef VRN_PHASE_TIMING
+__device__ unsigned long long vrn_phase_cycles[kPhaseSlots];
+#define VRN_PHASE_START()                              \
+  unsigned long long ph_[kPhaseSlots] = {};            \
+  unsigned long long tph_ = __builtin_amdgcn_s_memtime()
+#define VRN_PHASE(slot)                                               \
+  do {                                                                \
+    const unsigned long long tn_ = __builtin_amdgcn_s_memtime();     \
+    ph_[(slot)] += tn_ - tph_;                                        \
+    tph_ = tn_;                                                       \
+  } while (0)
+#define VRN_PHASE_FLUSH()                                                                  \
+  do {                                                                                     \
+    if (lane_id() == 0)                                                                    \
+      for (int i_ = 0; i_ < kPhaseSlots; ++i_) atomicAdd(&vrn_phase_cycles[i_], ph_[i_]); \
+  } while (0)
+#else
+#define VRN_PHASE_START() \
+  do {                    \
+  } while (0)
+#define VRN_PHASE(slot) \
+  do {                  \
+  } while (0)
+#define VRN_PHASE_FLUSH() \
+  do {                    \
+  } while (0)
+#endif
+
 // exp for compositing: the FP32 path keeps the library expf; the 16-bit
 // paths, whose inputs carry FP16 rounding already, use the hardware
 // exponential (one multiply and v_exp_f32).
@@ -216,6 +244,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
   uint32_t st_steps = 0, st_fetch = 0, st_samples = 0, st_rays = 0, st_rounds = 0, st_tiles = 0;
 
+  VRN_PHASE_START();
   auto retire = [&]() {
     float4 v = make_float4(cr, cg, cb, 1.0f - T);
     if (A.output != VRN_OUT_PQ) {
@@ -239,6 +268,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
     // keep LDS reads of weights inside the loop (hoisting would pin the
     // weights in registers and drop occupancy to one wave per SIMD)
     asm volatile("" ::: "memory");
+    VRN_PHASE(kPhComposite);
     // ---- 1. refill lanes that have no ray -------------------------------
     while (!out_of_work) {
       const uint64_t need = __ballot(pix == kNone);
@@ -281,6 +311,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
         if (++q_tried >= kQueues) out_of_work = true;
       }
     }
+    VRN_PHASE(kPhRefill);
     if (__ballot(pix != kNone) == 0) break;
     __builtin_amdgcn_wave_barrier();
 
@@ -308,6 +339,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
       st_tiles += (uint32_t)nt;
     }
 
+    VRN_PHASE(kPhMarch);
     // ---- 3. encode + MLP of the compacted samples -------------------------
     float so0 = 0.0f, sl0 = 0.0f, sl1 = 0.0f, sl2 = 0.0f;
     if constexpr (kF32Class<MODE>) {
@@ -324,8 +356,10 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
           shs[2] = v.z;
           shs[3] = v.w;
         }
+        VRN_PHASE(kPhEncode);
         float o0, lg[3];
         run_mlp<MODE>(s_w, s_b, F, feat, shs, lane, o0, lg);
+        VRN_PHASE(kPhMlp);
         const int from = rank & 15;
         const float a0 = shfl_f(o0, from), a1 = shfl_f(lg[0], from);
         const float a2 = shfl_f(lg[1], from), a3 = shfl_f(lg[2], from);
@@ -335,6 +369,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
           sl1 = a2;
           sl2 = a3;
         }
+        VRN_PHASE(kPhReturn);
       }
     } else {
       typedef Half8<MODE == 2> H;
@@ -361,6 +396,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
             }
             shh[t] = s_sh[(wave_base + src) * 4 + (lane >> 4)];
           }
+        VRN_PHASE(kPhEncode);
         float o0[kMlpBatch], lg[kMlpBatch][3];
         // The 16-bit MFMA chain co-executes with other waves' VALU and gather
         // issue, so the batch runs at raised issue priority: its dependent
@@ -370,6 +406,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
         __builtin_amdgcn_s_setprio(2);
         mlp_batch_16<MODE == 2, kMlpBatch>(reinterpret_cast<const uint4*>(s_w), s_b, cnt, xin, shh, lane, o0, lg);
         __builtin_amdgcn_s_setprio(0);
+        VRN_PHASE(kPhMlp);
         const int from = rank & 15;
 #pragma unroll
         for (int t = 0; t < kMlpBatch; ++t)
@@ -383,6 +420,7 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
               sl2 = a3;
             }
           }
+        VRN_PHASE(kPhReturn);
       }
     }
 
@@ -403,6 +441,8 @@ __global__ __launch_bounds__(kF32Class<MODE> ? kBlockF32 : kBlock, kF32Class<MOD
     }
   }
 
+  VRN_PHASE(kPhRefill);
+  VRN_PHASE_FLUSH();
   atomicAdd(&s_stats[0], st_rays);
   atomicAdd(&s_stats[1], st_samples);
   atomicAdd(&s_stats[2], st_fetch);
@@ -983,6 +1023,21 @@ hipError_t launch_set_occupancy(const FieldDev& F, const uint32_t* bits, hipStre
   hipLaunchKernelGGL(dilate_coarse_kernel, dim3((words + 255) / 256), dim3(256), 0, s, F,
                      const_cast<uint32_t*>(F.coarse_dil));
   return hipGetLastError();
+}
+
+hipError_t phase_cycles(unsigned long long out[kPhaseSlots], bool reset) {
+#ifdef VRN_PHASE_TIMING
+  hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(vrn_phase_cycles), sizeof(unsigned long long) * kPhaseSlots);
+  if (e == hipSuccess && reset) {
+    const unsigned long long zero[kPhaseSlots] = {};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(vrn_phase_cycles), zero, sizeof(zero));
+  }
+  return e;
+#else
+  (void)out;
+  (void)reset;
+  return hipErrorNotSupported;
+#endif
 }
 
 hipError_t debug_counters(unsigned long long out[kDbgSlots], bool reset) {

@@ -33,7 +33,7 @@ def main(lib_path):
     house16 = dict(house32, tables=house32["tables"].astype(np.float16))
     stereo = synth.cameras_house_stereo([150])[0]
     render(house16, stereo, 2048, 2048, ["f16", "bf16"])
-    render(house32, stereo, 2048, 2048, ["f32"])
+    render(house32, stereo, 2048, 2048, ["f32", "f32x"])
     del house32, house16
     render(synth.field_unbounded(), synth.cameras_unbounded(2, 256, 256), 256, 256, ["f32"])
     render(synth.field_unbounded(table_dtype=np.float16), synth.cameras_unbounded(2, 256, 256), 256, 256, ["f16"])
@@ -44,7 +44,7 @@ def main(lib_path):
     blob = synth.field_blobs64()
     fid = R.load(blob)
     bits = torch.zeros(((64 ** 3 + 31) // 32,), dtype=torch.int32, device="cuda")
-    for p in ("f16", "f32"):
+    for p in ("f16", "f32", "f32x"):
         capi.vrn_prune_grid(R.ctx, fid, 0.2, bits, None, 4, p)
     n = 4096
     g = torch.Generator().manual_seed(3)

@@ -2,7 +2,7 @@
 count, rather than trap on, hash-table offsets outside their level, brick
 and coarse-grid indices outside the grid, framebuffer writes outside the
 frame and NaN features or MLP outputs.  Every workload kind (the stereo
-house frame in FP16, BF16 and FP32; the unbounded scene; the exponential
+house frame in FP16, BF16, FP32 and FP32X; the unbounded scene; the exponential
 sample table; the room; grid pruning; the encode and MLP stage kernels) runs
 through a debug build in a child process and must leave every counter at
 zero, while an FP16 field whose weights overflow must be counted (the
