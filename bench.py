@@ -530,6 +530,11 @@ def main():
         fids_err = [int(x) for x in args.error_frames.split(",") if x]
         for p in paths:
             err[p] = pq_error(R, fids[p], field32, frames, fids_err, W, H, p, args.error_pixels)
+            if p in ("f16", "bf16"):
+                # against the oracle on the path's own FP16 tables: the 16-bit
+                # MLP arithmetic alone, without the tables' quantisation
+                own = pq_error(R, fids[p], field16, frames, fids_err, W, H, p, args.error_pixels)
+                err[p]["vs_oracle_on_fp16_tables"] = {k: own[k] for k in ("max_abs", "mean_abs", "psnr_pq")}
     head = "f16" if "f16" in results else paths[0]
     budget_ok = None
     if head in err:

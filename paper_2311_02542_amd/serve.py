@@ -304,9 +304,16 @@ def summarize(reqs, wall_s):
     lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
     wait = np.array([r.t_start - r.t_arrival for r in ok]) if ok else np.zeros(1)
     rays = sum(len(r.cams) * r.W * r.H for r in ok)
+    by_size = {}
+    for key in sorted({(len(r.cams), r.W, r.H) for r in ok}):
+        lk = np.array([r.latency for r in ok if (len(r.cams), r.W, r.H) == key])
+        by_size[f"{key[0]}x{key[1]}x{key[2]}"] = {"requests": int(lk.size),
+                                                 "p50_ms": float(np.percentile(lk, 50) * 1e3),
+                                                 "p99_ms": float(np.percentile(lk, 99) * 1e3)}
     return {"requests": len(reqs), "failed": len(reqs) - len(ok), "rays_per_s": rays / wall_s,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_ms": float(lat.mean() * 1e3), "wait_p50_ms": float(np.percentile(wait, 50) * 1e3)}
+            "mean_ms": float(lat.mean() * 1e3), "wait_p50_ms": float(np.percentile(wait, 50) * 1e3),
+            "by_size": by_size}
 
 
 def request_stream(n, rate_hz, seed=5004):
