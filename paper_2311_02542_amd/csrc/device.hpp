@@ -227,7 +227,7 @@ __device__ __forceinline__ void contract_point(const FieldDev& F, float x[3]) {
 // so table_next(t_k) equals t_{k+1} bit for bit.
 __device__ __forceinline__ float table_next(const FieldDev& F, float t) {
   const float g = F.step_growth * t;
-  return t + (g > F.dt ? g : F.dt);
+  return t + fmaxf(g, F.dt);  // both operands positive and finite
 }
 
 // Canonical position of the lattice sample at parameter t: x = o + t d
@@ -253,8 +253,25 @@ __device__ __forceinline__ void lattice_q(const FieldDev& F, const Ray& r, int k
   lattice_pos<GEO>(F, r, t, x, q);
 }
 
+// floor(q) with q clamped to [-1, G] first (no integer overflow far outside
+// the grid; q is never NaN): one med3 and one floor-and-convert.
 __device__ __forceinline__ int cell_of(float q, int G) {
-  return (int)floorf(fminf(fmaxf(q, -1.0f), (float)G));
+  const float c = __builtin_amdgcn_fmed3f(q, -1.0f, (float)G);
+  int i;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(c));
+  return i;
+}
+
+// x + n (y + n z) for the coarse-block and brick grids (n <= 256, indices
+// below 2^24): 24-bit multiplies issue at the full rate, where a 32-bit
+// multiply-add would take the quarter-rate 64-bit form.
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+__device__ __forceinline__ uint32_t grid_index(uint32_t x, uint32_t y, uint32_t z, uint32_t n) {
+  return mad_u24(n, mad_u24(n, z, y), x);
 }
 
 __device__ __forceinline__ bool bit_set(const uint32_t* bits, uint32_t idx) {
@@ -442,7 +459,7 @@ __device__ __forceinline__ float coarse_run(const FieldDev& F, const uint32_t* d
     y += ay ? st[1] : 0;
     z += az ? st[2] : 0;
     if (x < blo || y < blo || z < blo || x > bhi || y > bhi || z > bhi) break;
-    if (bit_set(dil, (uint32_t)x + (uint32_t)Gc * ((uint32_t)y + (uint32_t)Gc * (uint32_t)z))) break;
+    if (bit_set(dil, grid_index((uint32_t)x, (uint32_t)y, (uint32_t)z, (uint32_t)Gc))) break;
     tx += ax ? td[0] : 0.0f;
     ty += ay ? td[1] : 0.0f;
     tz += az ? td[2] : 0.0f;
@@ -477,7 +494,7 @@ __device__ __forceinline__ int contracted_run(const FieldDev& F, const uint32_t*
     for (int k = 0; k < 8; ++k) {
       const int x = b0[0] + (k & 1), y = b0[1] + ((k >> 1) & 1), z = b0[2] + (k >> 2);
       if (x <= b1[0] && y <= b1[1] && z <= b1[2])
-        clear = clear && !bit_set(dil, (uint32_t)x + (uint32_t)Gc * ((uint32_t)y + (uint32_t)Gc * (uint32_t)z));
+        clear = clear && !bit_set(dil, grid_index((uint32_t)x, (uint32_t)y, (uint32_t)z, (uint32_t)Gc));
     }
     return clear;
   };
@@ -508,7 +525,6 @@ template <int GEO>
 __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coarse, Ray& r, uint32_t budget,
                                           uint32_t& steps, float& st, float sx[3]) {
   const int G = (int)F.G;
-  const float cb = (float)(1u << F.cshift);
   // sample-table lattices: the parameter of sample r.k is carried from the
   // previous test (tk, valid while kt == r.k) by the table's own
   // recurrence, so stepping and box skips read no table entry
@@ -525,12 +541,11 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
       lattice_pos<GEO>(F, r, t, x, q);
     }
     const int cx = cell_of(q[0], G), cy = cell_of(q[1], G), cz = cell_of(q[2], G);
-    // empty box to try to jump over: origin (in units of its size) and size
-    int bo[3] = {0, 0, 0};
-    float bsize = 0.0f;
+    // empty box to try to jump over: the cell's block of 2^bsh cells (-1: none)
+    int bsh = -1;
     if ((unsigned)cx < (unsigned)G && (unsigned)cy < (unsigned)G && (unsigned)cz < (unsigned)G) {
       const int bx = cx >> F.cshift, by = cy >> F.cshift, bz = cz >> F.cshift;
-      const uint32_t ci = (uint32_t)bx + F.Gc * ((uint32_t)by + F.Gc * (uint32_t)bz);
+      const uint32_t ci = grid_index((uint32_t)bx, (uint32_t)by, (uint32_t)bz, F.Gc);
       VRN_DEBUG_COUNT(ci >= F.Gc * F.Gc * F.Gc, kDbgCoarse);
       if (!bit_set(coarse, ci)) {
         if (!bit_set(coarse + kCoarseWords, ci)) {
@@ -576,13 +591,10 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
             continue;
           }
         }
-        bo[0] = bx;
-        bo[1] = by;
-        bo[2] = bz;
-        bsize = cb;
+        bsh = (int)F.cshift;
       } else {
         const int kx = cx >> 2, ky = cy >> 2, kz = cz >> 2;
-        const int brick = kx + (int)F.Gb * (ky + (int)F.Gb * kz);
+        const int brick = (int)grid_index((uint32_t)kx, (uint32_t)ky, (uint32_t)kz, F.Gb);
         if (brick != r.brick) {
           VRN_DEBUG_COUNT((uint32_t)brick >= F.Gb * F.Gb * F.Gb, kDbgBrick);
           const unsigned long long b = F.bricks[brick];
@@ -591,14 +603,11 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
           r.bhi = (uint32_t)(b >> 32);
         }
         if ((r.blo | r.bhi) == 0u) {
-          bo[0] = kx;
-          bo[1] = ky;
-          bo[2] = kz;
-          bsize = 4.0f;
+          bsh = 2;
         } else {
-          const uint32_t bit = (uint32_t)((cx & 3) + 4 * (cy & 3) + 16 * (cz & 3));
-          const uint32_t word = bit < 32u ? r.blo : r.bhi;
-          if ((word >> (bit & 31u)) & 1u) {
+          const uint32_t bit = (uint32_t)((cx & 3) | ((cy & 3) << 2) | ((cz & 3) << 4));
+          const unsigned long long bits = ((unsigned long long)r.bhi << 32) | r.blo;
+          if ((bits >> bit) & 1ull) {
             st = t;
             sx[0] = x[0];
             sx[1] = x[1];
@@ -610,7 +619,8 @@ __device__ __forceinline__ int march_next(const FieldDev& F, const uint32_t* coa
       }
     }
     float t_land = 0.0f;   // table entries are > 0: 0 means not known
-    const bool moved = bsize > 0.0f && skip_box<GEO>(F, r, q, bo[0], bo[1], bo[2], bsize, t_land);
+    const bool moved =
+        bsh >= 0 && skip_box<GEO>(F, r, q, cx >> bsh, cy >> bsh, cz >> bsh, (float)(1 << bsh), t_land);
     if constexpr (GEO == 1) {
       // the next test's parameter: the successor of this one, or of the
       // landing sample of a straight skip (r.k is then already past it);
