@@ -698,10 +698,15 @@ __device__ __forceinline__ void corner_offsets(const FieldDev& F, const LevelDev
 #pragma unroll
     for (int c = 0; c < 8; ++c) off[c] = ((c & 1) ? x1 : x0) + ((c & 2) ? hy1 : hy0) + ((c & 4) ? hz1 : hz0);
   } else {
+    // both formulas, then a bitwise select by the lane's level (no branches)
+    const uint32_t dm = 0u - P.dense;  // all ones for a dense level
+    const uint32_t xb0 = hx0 + P.base, xb1 = hx1 + P.base;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const uint32_t a = (c & 1) ? hx1 : hx0, b = (c & 2) ? hy1 : hy0, e = (c & 4) ? hz1 : hz0;
-      off[c] = P.dense ? (a + b + e) + P.base : (((a ^ b ^ e) & m) | P.base);
+      const uint32_t od = ((c & 1) ? xb1 : xb0) + b + e;
+      const uint32_t oh = ((a ^ b ^ e) & m) | P.base;
+      off[c] = (od & dm) | (oh & ~dm);
     }
   }
 }
