@@ -254,9 +254,11 @@ __device__ __forceinline__ void lattice_q(const FieldDev& F, const Ray& r, int k
 }
 
 // floor(q) with q clamped to [-1, G] first (no integer overflow far outside
-// the grid; q is never NaN): one med3 and one floor-and-convert.
+// the grid; q is never NaN), the floor and the conversion in one instruction.
+// (A med3 clamp would save one more, but costs the FP32X kernel scratch
+// spills.)
 __device__ __forceinline__ int cell_of(float q, int G) {
-  const float c = __builtin_amdgcn_fmed3f(q, -1.0f, (float)G);
+  const float c = fminf(fmaxf(q, -1.0f), (float)G);
   int i;
   asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(c));
   return i;
